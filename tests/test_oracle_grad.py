@@ -1,0 +1,92 @@
+"""Pins of the oracle's analytic adjoint against high-precision finite differences of
+the forward (Section 2.1, Eq. 1 differentiated), plus conservation laws of the gradient.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+
+
+def _case(seed, n=6, m=3, dim=2, hit=False):
+    r = np.random.default_rng(3000 + seed)
+    x = r.random((n, dim)).astype(np.float32).astype(np.float64)
+    z = r.normal(size=n).astype(np.float32).astype(np.float64)
+    q = r.random((m, dim)).astype(np.float32).astype(np.float64)
+    g = r.normal(size=m)
+    if hit:
+        q[0] = x[2]
+    return x, z, q, g
+
+
+@pytest.mark.parametrize("p,dim,hit", [("2", 2, False), ("2.5", 3, False), ("1.5", 2, True), ("3", 3, True)])
+def test_analytic_gradient_matches_decimal_finite_differences(p, dim, hit):
+    x, z, q, g = _case(int(float(p) * 10) + dim, dim=dim, hit=hit)
+    fd = exact.gradients_fd([tuple(r) for r in x], z, [tuple(r) for r in q], p, g)
+    an = oracle.backward(x, z, q, float(p), g)
+    np.testing.assert_allclose(an["dz"], fd["dz"], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(an["dq"], np.array(fd["dq"]), rtol=1e-11, atol=1e-12)
+    assert an["dp"] == pytest.approx(fd["dp"], rel=1e-11, abs=1e-13)
+
+
+def test_value_gradient_sums_to_upstream_gradient():
+    # Weights are normalised, so sum_j dZ_i/dz_j = 1 for every query.
+    x, z, q, g = _case(21, n=80, m=30, dim=3)
+    an = oracle.backward(x, z, q, 2.0, g)
+    assert np.sum(an["dz"]) == pytest.approx(np.sum(g), rel=1e-13)
+
+
+def test_constant_field_has_no_position_or_power_gradient():
+    x, _, q, g = _case(22, n=50, m=10)
+    an = oracle.backward(x, np.full(50, 0.75), q, 2.5, g)
+    assert an["dp"] == pytest.approx(0.0, abs=1e-13)
+    np.testing.assert_allclose(an["dq"], 0.0, atol=1e-12)
+
+
+def test_hit_gradient_goes_to_the_coincident_points_only():
+    x, z, q, g = _case(23, n=10, m=2)
+    x[4] = x[1]
+    q[0] = x[1]
+    an = oracle.backward(x, z, q[:1], 2.0, g[:1])
+    expect = np.zeros(10)
+    expect[[1, 4]] = g[0] / 2
+    np.testing.assert_allclose(an["dz"], expect, rtol=1e-15, atol=0)
+    assert an["dp"] == 0.0
+    np.testing.assert_array_equal(an["dq"], 0.0)
+
+
+def test_scales_bound_gradients():
+    x, z, q, g = _case(24, n=60, m=12, dim=2)
+    an = oracle.backward(x, z, q, 2.0, g)
+    assert np.all(np.abs(an["dz"]) <= an["dz_scale"] * (1 + 1e-14))
+    assert abs(an["dp"]) <= an["dp_scale"] * (1 + 1e-14)
+    assert np.all(np.max(np.abs(an["dq"]), axis=1) <= an["dq_scale"] * (1 + 1e-14))
+
+
+def test_leave_one_out_equals_explicit_deletion():
+    r = np.random.default_rng(25)
+    n = 48
+    x = r.random((n, 2))
+    z = r.normal(size=n)
+    idx = np.arange(n)
+    loo = oracle.forward(x, z, x, 2.0, self_index=idx)
+    g = r.normal(size=n)
+    bl = oracle.backward(x, z, x, 2.0, g, self_index=idx)
+    dz = np.zeros(n)
+    dp = 0.0
+    for i in range(n):
+        keep = np.array([j for j in range(n) if j != i])
+        one = oracle.forward(x[keep], z[keep], x[i:i + 1], 2.0)
+        assert loo["Z"][i] == pytest.approx(one["Z"][0], rel=1e-15, abs=1e-15)
+        b1 = oracle.backward(x[keep], z[keep], x[i:i + 1], 2.0, g[i:i + 1])
+        dz[keep] += b1["dz"]
+        dp += b1["dp"]
+        np.testing.assert_allclose(bl["dq"][i], b1["dq"][0], rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(bl["dz"], dz, rtol=1e-13, atol=1e-15)
+    assert bl["dp"] == pytest.approx(dp, rel=1e-12)
+
+
+def test_loo_loss_of_constant_field_is_zero():
+    r = np.random.default_rng(26)
+    x = r.random((40, 2))
+    assert oracle.loo_loss(x, np.full(40, 2.0), 1.5) == pytest.approx(0.0, abs=1e-28)

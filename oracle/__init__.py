@@ -48,7 +48,7 @@ def _load():
                                                ctypes.c_double, ip, dp, dp, dp, ip]
             lib.idw_oracle_forward.restype = ctypes.c_int
             lib.idw_oracle_backward.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
-                                                ctypes.c_double, ip, dp, dp, dp, dp, dp, dp, dp]
+                                                ctypes.c_double, ip, dp, dp, dp, dp, dp, dp, dp, dp, dp]
             lib.idw_oracle_backward.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -97,7 +97,12 @@ def forward(x, z, q, p, self_index=None):
 
 
 def backward(x, z, q, p, g, self_index=None):
-    """Analytic adjoint of Eq. 1.  Returns dict(dz, dp, dq, dz_scale, dp_scale, dq_scale)."""
+    """Analytic adjoint of Eq. 1.
+
+    Returns dict(dz, dp, dq, dz_scale, dp_scale, dq_scale, dp_cond, dq_cond): the *_scale
+    entries are the sums of absolute terms; dp_cond / dq_cond the uncentred sums that
+    measure how far a relative perturbation of the values moves dp / dq.
+    """
     lib = _load()
     x, z, q, si = _prep(x, z, q, self_index)
     g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
@@ -111,12 +116,14 @@ def backward(x, z, q, p, g, self_index=None):
     dps = np.empty(1)
     dq = np.empty((m, dim))
     dqs = np.empty(m)
+    dpc = np.empty(1)
+    dqc = np.empty(m)
     rc = lib.idw_oracle_backward(n, dim, _d(x), _d(z), m, _d(q), float(p), _i(si), _d(g), _d(dz), _d(dp),
-                                 _d(dq), _d(dzs), _d(dps), _d(dqs))
+                                 _d(dq), _d(dzs), _d(dps), _d(dqs), _d(dpc), _d(dqc))
     if rc != 0:
         raise ValueError("oracle backward: invalid arguments")
     return {"dz": dz, "dp": float(dp[0]), "dq": dq, "dz_scale": dzs, "dp_scale": float(dps[0]),
-            "dq_scale": dqs}
+            "dq_scale": dqs, "dp_cond": float(dpc[0]), "dq_cond": dqc}
 
 
 def loo_loss(x, z, p, idx=None):

@@ -110,11 +110,15 @@ int idw_oracle_forward(int64_t n, int dim, const double* x, const double* z, int
  *   dz_scale[n] = sum_i |g_i| w_ij / D_i,  dp_scale[1] = sum_i |g_i| (1/D_i) sum_j |term|,
  *   dq_scale[m] = |g_i| (p/D_i) sum_j (w/r2) |z_j - Z_i| |q_i - x_j|,
  * which bound the conditioning of each sum (errors are stated relative to them).
+ * The dp and dq sums are centred on Z_i; near a data point z_j - Z_i is tiny and those
+ * sums become sensitive to the last bits of z and Z (a relative perturbation e of the
+ * values moves them by about e times the uncentred sums).  dp_cond / dq_cond give those
+ * uncentred sums, with |z_j| + |Z_i| in place of |z_j - Z_i| (nullable).
  */
 int idw_oracle_backward(int64_t n, int dim, const double* x, const double* z, int64_t m,
                         const double* q, double p, const int64_t* self_index, const double* g,
                         double* dz, double* dp, double* dq, double* dz_scale,
-                        double* dp_scale, double* dq_scale) {
+                        double* dp_scale, double* dq_scale, double* dp_cond, double* dq_cond) {
   if (n < 1 || m < 0 || (dim != 2 && dim != 3) || !(p > 0.0) || !x || !z || (m && (!q || !g)))
     return -1;
   nsum* dzs = (nsum*)calloc((size_t)n, sizeof(nsum));
@@ -124,7 +128,7 @@ int idw_oracle_backward(int64_t n, int dim, const double* x, const double* z, in
     free(dza);
     return -1;
   }
-  nsum dpt = {0, 0}, dpa = {0, 0};
+  nsum dpt = {0, 0}, dpa = {0, 0}, dpc = {0, 0};
   for (int64_t i = 0; i < m; ++i) {
     const double* qi = q + i * dim;
     double Zi, Di;
@@ -148,9 +152,11 @@ int idw_oracle_backward(int64_t n, int dim, const double* x, const double* z, in
       if (dq)
         for (int k = 0; k < dim; ++k) dq[i * dim + k] = 0.0;
       if (dq_scale) dq_scale[i] = 0.0;
+      if (dq_cond) dq_cond[i] = 0.0;
       continue;
     }
-    nsum P = {0, 0}, Pa = {0, 0}, G[3] = {{0, 0}, {0, 0}, {0, 0}}, Ga = {0, 0};
+    nsum P = {0, 0}, Pa = {0, 0}, Pc = {0, 0}, G[3] = {{0, 0}, {0, 0}, {0, 0}}, Ga = {0, 0},
+         Gc = {0, 0};
     for (int64_t j = 0; j < n; ++j) {
       if (self_index && self_index[i] == j) continue;
       const double* xj = x + j * dim;
@@ -160,6 +166,8 @@ int idw_oracle_backward(int64_t n, int dim, const double* x, const double* z, in
       double lp = w * 0.5 * log(r2) * c;
       nadd(&P, lp);
       nadd(&Pa, fabs(lp));
+      const double cabs = fabs(z[j]) + fabs(Zi);
+      nadd(&Pc, fabs(w * 0.5 * log(r2)) * cabs);
       double u = (w / r2) * c;
       double ua = 0.0;
       for (int k = 0; k < dim; ++k) {
@@ -168,14 +176,17 @@ int idw_oracle_backward(int64_t n, int dim, const double* x, const double* z, in
         ua += fabs(dk);
       }
       nadd(&Ga, fabs(u) * ua);
+      nadd(&Gc, (w / r2) * cabs * ua);
       nadd(&dzs[j], gi * w / Di);
       nadd(&dza[j], fabs(gi) * w / Di);
     }
     nadd(&dpt, -gi * nval(&P) / Di);
     nadd(&dpa, fabs(gi) * nval(&Pa) / Di);
+    nadd(&dpc, fabs(gi) * nval(&Pc) / Di);
     if (dq)
       for (int k = 0; k < dim; ++k) dq[i * dim + k] = -(p * gi / Di) * nval(&G[k]);
     if (dq_scale) dq_scale[i] = fabs(p * gi / Di) * nval(&Ga);
+    if (dq_cond) dq_cond[i] = fabs(p * gi / Di) * nval(&Gc);
   }
   for (int64_t j = 0; j < n; ++j) {
     if (dz) dz[j] = nval(&dzs[j]);
@@ -183,6 +194,7 @@ int idw_oracle_backward(int64_t n, int dim, const double* x, const double* z, in
   }
   if (dp) dp[0] = nval(&dpt);
   if (dp_scale) dp_scale[0] = nval(&dpa);
+  if (dp_cond) dp_cond[0] = nval(&dpc);
   free(dzs);
   free(dza);
   return 0;

@@ -61,6 +61,9 @@ def test_scales_bound_gradients():
     assert np.all(np.abs(an["dz"]) <= an["dz_scale"] * (1 + 1e-14))
     assert abs(an["dp"]) <= an["dp_scale"] * (1 + 1e-14)
     assert np.all(np.max(np.abs(an["dq"]), axis=1) <= an["dq_scale"] * (1 + 1e-14))
+    # the uncentred condition sums dominate the centred ones: |z - Z| <= |z| + |Z|
+    assert np.all(an["dq_scale"] <= an["dq_cond"] * (1 + 1e-14))
+    assert an["dp_scale"] <= an["dp_cond"] * (1 + 1e-14)
 
 
 def test_leave_one_out_equals_explicit_deletion():

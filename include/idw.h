@@ -1,0 +1,182 @@
+/*
+ * idw.h - C ABI of the MI355X (gfx950) Shepard IDW library (libidw.so).
+ *
+ * The library evaluates Shepard's inverse-distance-weighting interpolant (Section 2.1,
+ * Eq. 1 of Mei & Tian, "Performance Impact of Data Layout on the GPU-accelerated IDW
+ * Interpolation"):
+ *
+ *     Z(q) = sum_j w_j(q) z_j / sum_j w_j(q),      w_j(q) = d(q, x_j)^-p,
+ *
+ * over ALL n data points (global IDW), d the Euclidean distance over dim = 2 or 3
+ * coordinates, p > 0 real.  Where Eq. 1 is undefined (d = 0) the result is the mean value
+ * of the data points that coincide exactly with q.
+ *
+ * Conventions shared by every entry point
+ *  - Every array pointer is a DEVICE pointer owned by the caller.  The library never frees,
+ *    retains or reallocates them; it reads inputs and writes outputs only.
+ *  - All work is enqueued asynchronously on `stream` (a hipStream_t passed as void*; NULL
+ *    is the legacy default stream).  Entry points never synchronise and never allocate
+ *    device memory, except idw_batched_plan_create (documented there).
+ *  - Arguments are validated on the host before anything is enqueued; on failure nothing is
+ *    enqueued and a non-zero status is returned; idw_last_error() describes it.  Input
+ *    values are not scanned: NaN or infinite coordinates/values give undefined results.
+ *  - Results are bitwise reproducible for fixed inputs, sizes and configuration (no
+ *    floating-point atomics; every reduction has a fixed order).
+ *  - Element type follows the precision: IDW_FP32 reads and writes float arrays,
+ *    IDW_FP64 reads and writes double arrays.  Denominators (out_den, saved_den) and
+ *    grad_p are always double.
+ */
+#ifndef IDW_H
+#define IDW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+  IDW_OK = 0,
+  IDW_EINVAL = 1,        /* bad argument (size, pointer, alignment, enum, p) */
+  IDW_EDEVICE = 2,       /* no usable gfx950 device, or a HIP runtime error */
+  IDW_ENOMEM = 3,        /* host/device allocation failed (plan creation only) */
+  IDW_EUNSUPPORTED = 4,  /* valid but unsupported combination */
+  IDW_EWORKSPACE = 5     /* workspace pointer missing, misaligned or too small */
+};
+
+/* Record layouts of a point set (Sections 3.1-3.5).  T is float (IDW_FP32) or double.
+ * Data points carry coordinates and a value v; query points carry coordinates only.
+ *   IDW_SOA    (Section 3.1) ptr[0..dim-1] = coordinate arrays T[n]; data: ptr[dim] = v[n].
+ *   IDW_AOS    (Section 3.2) ptr[0] = packed records {x, y, (z), v} (queries {x, y, (z)}),
+ *              no padding, T-aligned.
+ *   IDW_AOAS   (Section 3.3, also the built-in float4/double4 form) ptr[0] = records of
+ *              four T: {x, y, v, pad} / {x, y, z, v} (queries {x, y, (z), pad}); 16-byte
+ *              (float) or 32-byte (double) aligned.
+ *   IDW_HYBRID (Section 3.5, AoS + array of values) ptr[0] = packed coordinate records
+ *              {x, y, (z)}; data: ptr[1] = v[n].
+ *   IDW_SOAOS  (Section 3.4) ptr[0] = aligned coordinate records {x, y} (dim 2) or
+ *              {x, y, z, pad} (dim 3), aligned to their size; data: ptr[1] = aligned
+ *              value records {v, pad}. */
+enum { IDW_SOA = 0, IDW_AOS = 1, IDW_AOAS = 2, IDW_HYBRID = 3, IDW_SOAOS = 4 };
+
+/* Precision of the sweep.
+ *   IDW_FP32: float inputs/outputs.  The all-pairs sweep runs in FP32 with blocked
+ *     compensated sums (plain FP32 inside 64-point blocks, TwoSum merge of each block into
+ *     hi/lo pairs); the ratio is taken in FP64; queries closer than 1e-6 of the data
+ *     extent to a data point (including exact hits) are recomputed entirely in FP64.
+ *   IDW_FP64: double inputs/outputs, FP64 sweep with the same blocked compensation. */
+enum { IDW_FP32 = 0, IDW_FP64 = 1 };
+
+/* Flags. */
+#define IDW_EXCLUDE_SELF 0x1u /* leave-one-out: queries ARE the data set (m == n, same
+                                 points in the same order); pair (i, i) is skipped */
+#define IDW_NEED_DZ 0x2u      /* idw_backward: compute grad_z */
+#define IDW_NEED_DP 0x4u      /* idw_backward: compute grad_p */
+#define IDW_NEED_DQ 0x8u      /* idw_backward: compute grad_q */
+
+/* A point set.  n >= 0; dim 2 or 3; layout one of IDW_SOA..IDW_SOAOS; unused ptr[] slots
+ * are ignored.  For data points n >= 1. */
+typedef struct idw_points {
+  const void* ptr[4];
+  int64_t n;
+  int32_t dim;
+  int32_t layout;
+} idw_points;
+
+/* Optional launch configuration; zero fields select the library default.
+ *   queries_per_lane  queries held in registers per lane of the sweep (FP32: 1,2,4,8;
+ *                     FP64: 1,2,4)
+ *   split             number of data chunks swept by separate workgroups and merged in a
+ *                     fixed order (1..1024); 0 = chosen from m so the chip is filled. */
+typedef struct idw_config {
+  int32_t queries_per_lane;
+  int32_t split;
+  int32_t reserved[6];
+} idw_config;
+
+/* Library version string (static storage). */
+const char* idw_version(void);
+
+/* Description of the last error raised on the calling thread (static thread-local
+ * storage, valid until the next call on that thread). */
+const char* idw_last_error(void);
+
+/* Bytes of a record of `layout` for dim and precision, per pointer slot: writes
+ * bytes[0..3] (0 for unused slots).  For data (is_data != 0) or query records.  Host
+ * only; never touches the device.  Returns IDW_OK or IDW_EINVAL. */
+int idw_record_bytes(int32_t layout, int32_t dim, int32_t precision, int32_t is_data,
+                     size_t bytes[4]);
+
+/* Device workspace needed by idw_forward and idw_backward for these point sets, with
+ * `cfg` (nullable).  One workspace serves both calls.  Host only. */
+int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t precision,
+                       const idw_config* cfg, size_t* bytes);
+
+/* Forward sweep (Eq. 1).
+ *   data, query  point sets (device memory); query->n == m may be 0 (no-op).
+ *   p            power parameter, finite, 0 < p <= 64.
+ *   flags        0 or IDW_EXCLUDE_SELF.
+ *   out_z        [m] interpolated values, element type of `precision`.
+ *   out_den      [m] double denominators sum_j w_j in the caller's units (nullable);
+ *                +inf for queries that coincide exactly with a data point.  Needed by
+ *                idw_backward.
+ *   workspace    device buffer of at least idw_workspace_size() bytes, 256-byte aligned;
+ *                its contents on entry are irrelevant and on exit unspecified.
+ * The workspace is in use until the enqueued work completes; concurrent calls must use
+ * different workspaces. */
+int idw_forward(const idw_points* data, const idw_points* query, double p, int32_t precision,
+                uint32_t flags, void* out_z, double* out_den, void* workspace,
+                size_t workspace_bytes, void* stream, const idw_config* cfg);
+
+/* Adjoint of idw_forward: given grad_out[i] = dL/dZ_i, writes
+ *   grad_z [n]       dL/dz_j   (element type of precision)   if flags & IDW_NEED_DZ
+ *   grad_p [1]       dL/dp     (double, device)              if flags & IDW_NEED_DP
+ *   grad_q [m*dim]   dL/dq_i   row-major, element type       if flags & IDW_NEED_DQ
+ * saved_z / saved_den are idw_forward's out_z / out_den for the same inputs and p.  The
+ * formulas are those of Eq. 1 differentiated: dZ_i/dz_j = w_ij / D_i,
+ * dZ_i/dp = -(1/D_i) sum_j w_ij (1/2) ln(d_ij^2) (z_j - Z_i),
+ * dZ_i/dq_i = -(p/D_i) sum_j (w_ij / d_ij^2) (z_j - Z_i)(q_i - x_j); at an exact hit with h
+ * coincident points, dZ_i/dz_j = 1/h for each of them and the other terms are 0.
+ * Queries within 1e-6 of the extent of a data point are handled in FP64. */
+int idw_backward(const idw_points* data, const idw_points* query, double p, int32_t precision,
+                 uint32_t flags, const void* grad_out, const void* saved_z,
+                 const double* saved_den, void* grad_z, double* grad_p, void* grad_q,
+                 void* workspace, size_t workspace_bytes, void* stream, const idw_config* cfg);
+
+/* ---- Batched form: many independent instances in one persistent launch. ---- */
+
+/* One instance: its own data, queries, p and outputs (device pointers). */
+typedef struct idw_instance {
+  idw_points data;
+  idw_points query;
+  double p;
+  void* out_z;      /* [query.n], element type of the plan precision */
+  double* out_den;  /* [query.n], nullable */
+} idw_instance;
+
+typedef struct idw_plan idw_plan;
+
+/* Builds a plan for `count` instances (host descriptors, copied).  Only IDW_FP32 with
+ * integer p in {1, 2, 3} or any p > 0 is accepted; every instance uses the IDW_AOAS layout
+ * or any other layout (per instance).  The plan owns a device work list that it allocates
+ * here (the only allocating entry point) and a HIP graph that is captured on the first
+ * idw_batched call for a given workspace.  `cfg` may be NULL. */
+int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_t precision,
+                            const idw_config* cfg, idw_plan** out_plan);
+
+/* Device workspace bytes needed by idw_batched for this plan. */
+int idw_batched_plan_workspace(const idw_plan* plan, size_t* bytes);
+
+/* Runs every instance of the plan: one graph launch on `stream`. */
+int idw_batched(idw_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Releases the plan (synchronises with the device first). */
+void idw_batched_plan_destroy(idw_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IDW_H */

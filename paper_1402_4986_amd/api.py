@@ -1,0 +1,213 @@
+"""Python face of libidw: point descriptors, forward/backward calls, the autograd Function
+and the leave-one-out fit of p.
+
+PyTorch provides device memory and streams only; every step of the IDW path (extent,
+sweeps, merges, FP64 fix-ups, reductions) runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import IdwConfig, IdwPoints, check
+
+_TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64}
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+@dataclass
+class Points:
+    """A point set in one of the record layouts (device tensors, caller-owned).
+
+    tensors: one contiguous tensor per pointer slot of the layout (see include/idw.h);
+    n: number of points; dim: 2 or 3; layout: 'soa' | 'aos' | 'aoas' | 'hybrid' | 'soaos'.
+    """
+    tensors: Sequence[torch.Tensor]
+    n: int
+    dim: int
+    layout: str
+
+    def c(self) -> IdwPoints:
+        s = IdwPoints()
+        for k, t in enumerate(self.tensors):
+            if not t.is_contiguous():
+                raise ValueError("point tensors must be contiguous")
+            s.ptr[k] = t.data_ptr()
+        s.n = int(self.n)
+        s.dim = int(self.dim)
+        s.layout = _lib.LAYOUT_CODES[self.layout]
+        return s
+
+    @property
+    def device(self) -> torch.device:
+        return self.tensors[0].device
+
+    @property
+    def dtype(self) -> torch.dtype:
+        return self.tensors[0].dtype
+
+    @staticmethod
+    def from_arrays(arrays, n: int, dim: int, layout: str, device="cuda") -> "Points":
+        """Upload host arrays (already packed in `layout`) to the device."""
+        ts = [torch.as_tensor(a).to(device).contiguous() for a in arrays]
+        return Points(ts, n, dim, layout)
+
+    @staticmethod
+    def hybrid(coords: torch.Tensor, values: Optional[torch.Tensor] = None) -> "Points":
+        """Coordinates [n, dim] (packed rows) plus an optional value array [n]."""
+        ts = [coords.contiguous()] + ([values.contiguous()] if values is not None else [])
+        return Points(ts, coords.shape[0], coords.shape[1], "hybrid")
+
+
+def _cfg(queries_per_lane: int = 0, split: int = 0) -> Optional[IdwConfig]:
+    if not queries_per_lane and not split:
+        return None
+    c = IdwConfig()
+    c.queries_per_lane = queries_per_lane
+    c.split = split
+    return c
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+_ws_cache: dict = {}
+
+
+def workspace(data: Points, query: Points, precision: str, cfg: Optional[IdwConfig] = None) -> torch.Tensor:
+    """A device workspace large enough for forward and backward on these point sets
+    (cached per device and grown on demand)."""
+    lib = _lib.load()
+    need = ctypes.c_size_t()
+    dc, qc = data.c(), query.c()
+    check(lib.idw_workspace_size(ctypes.byref(dc), ctypes.byref(qc), _lib.PRECISION_CODES[precision],
+                                 ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(need)))
+    key = (str(data.device),)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device=data.device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def forward(data: Points, query: Points, p: float, precision: str = "f32", exclude_self: bool = False,
+            queries_per_lane: int = 0, split: int = 0, out_z: Optional[torch.Tensor] = None,
+            out_den: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+    """Z[m] (precision dtype) and D[m] (float64) for the query set (Eq. 1)."""
+    lib = _lib.load()
+    dt = _TORCH_DTYPE[precision]
+    m = int(query.n)
+    dev = data.device
+    if out_z is None:
+        out_z = torch.empty(m, dtype=dt, device=dev)
+    if out_den is None:
+        out_den = torch.empty(m, dtype=torch.float64, device=dev)
+    cfg = _cfg(queries_per_lane, split)
+    if ws is None:
+        ws = workspace(data, query, precision, cfg)
+    dc, qc = data.c(), query.c()
+    check(lib.idw_forward(ctypes.byref(dc), ctypes.byref(qc), float(p), _lib.PRECISION_CODES[precision],
+                          _lib.EXCLUDE_SELF if exclude_self else 0, _ptr(out_z), _ptr(out_den), _ptr(ws),
+                          ws.numel(), _stream_handle(dev), ctypes.byref(cfg) if cfg is not None else None))
+    return out_z, out_den
+
+
+def backward(data: Points, query: Points, p: float, grad_out: torch.Tensor, saved_z: torch.Tensor,
+             saved_den: torch.Tensor, precision: str = "f32", need_dz: bool = True, need_dp: bool = True,
+             need_dq: bool = True, exclude_self: bool = False, ws: Optional[torch.Tensor] = None):
+    """(dz[n] or None, dp (0-d float64 tensor) or None, dq[m, dim] or None)."""
+    lib = _lib.load()
+    dt = _TORCH_DTYPE[precision]
+    dev = data.device
+    n, m, dim = int(data.n), int(query.n), int(data.dim)
+    dz = torch.empty(n, dtype=dt, device=dev) if need_dz else None
+    dp = torch.empty((), dtype=torch.float64, device=dev) if need_dp else None
+    dq = torch.empty((m, dim), dtype=dt, device=dev) if need_dq else None
+    flags = (_lib.EXCLUDE_SELF if exclude_self else 0) | (_lib.NEED_DZ if need_dz else 0) \
+        | (_lib.NEED_DP if need_dp else 0) | (_lib.NEED_DQ if need_dq else 0)
+    if ws is None:
+        ws = workspace(data, query, precision)
+    dc, qc = data.c(), query.c()
+    check(lib.idw_backward(ctypes.byref(dc), ctypes.byref(qc), float(p), _lib.PRECISION_CODES[precision], flags,
+                           _ptr(grad_out.contiguous()), _ptr(saved_z), _ptr(saved_den), _ptr(dz), _ptr(dp),
+                           _ptr(dq), _ptr(ws), ws.numel(), _stream_handle(dev), None))
+    return dz, dp, dq
+
+
+def _precision_of(t: torch.Tensor) -> str:
+    if t.dtype == torch.float32:
+        return "f32"
+    if t.dtype == torch.float64:
+        return "f64"
+    raise TypeError("IDW tensors must be float32 or float64")
+
+
+class IDWFunction(torch.autograd.Function):
+    """Z = IDW(X, z, Q, p) with X [n, dim] data coordinates, z [n] values, Q [m, dim]
+    queries and p a 0-d tensor.  Gradients flow to z, Q and p (not to X)."""
+
+    @staticmethod
+    def forward(ctx, X, z, Q, p, exclude_self=False):
+        prec = _precision_of(X)
+        pv = float(p)
+        data = Points.hybrid(X, z)
+        query = Points.hybrid(Q)
+        Z, D = forward(data, query, pv, prec, exclude_self=exclude_self)
+        ctx.save_for_backward(X, z, Q, Z, D)
+        ctx.pv = pv
+        ctx.prec = prec
+        ctx.excl = exclude_self
+        ctx.p_dtype = p.dtype if torch.is_tensor(p) else torch.float64
+        return Z
+
+    @staticmethod
+    def backward(ctx, gZ):
+        X, z, Q, Z, D = ctx.saved_tensors
+        need_x, need_z, need_q, need_p = ctx.needs_input_grad[:4]
+        if need_x:
+            raise NotImplementedError("the gradient with respect to data coordinates is not provided")
+        if not (need_z or need_q or need_p):
+            return None, None, None, None, None
+        data = Points.hybrid(X, z)
+        query = Points.hybrid(Q)
+        dz, dp, dq = backward(data, query, ctx.pv, gZ.to(Z.dtype).contiguous(), Z, D, ctx.prec, need_dz=need_z,
+                              need_dp=need_p, need_dq=need_q, exclude_self=ctx.excl)
+        return None, dz, dq, (dp.to(ctx.p_dtype) if dp is not None else None), None
+
+
+def interpolate(X: torch.Tensor, z: torch.Tensor, Q: torch.Tensor, p=2.0) -> torch.Tensor:
+    """Differentiable Shepard IDW of values z at X, evaluated at Q."""
+    if not torch.is_tensor(p):
+        p = torch.tensor(float(p), dtype=torch.float64, device=X.device)
+    return IDWFunction.apply(X, z, Q, p)
+
+
+def loo_loss(X: torch.Tensor, z: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
+    """Leave-one-out mean squared error of IDW at the data points."""
+    Z = IDWFunction.apply(X, z, X, p, True)
+    return torch.mean((Z.to(torch.float64) - z.to(torch.float64)) ** 2)
+
+
+def fit_p_loo(X: torch.Tensor, z: torch.Tensor, p0: float = 1.5, steps: int = 50, lr: float = 0.05,
+              clamp=(0.05, 6.0)):
+    """Fits p by Adam on the leave-one-out loss; returns (p, history of (p, loss))."""
+    p = torch.tensor(float(p0), dtype=torch.float64, device=X.device, requires_grad=True)
+    opt = torch.optim.Adam([p], lr=lr)
+    hist = []
+    for _ in range(steps):
+        opt.zero_grad()
+        loss = loo_loss(X, z, p)
+        loss.backward()
+        hist.append((float(p.detach()), float(loss.detach())))
+        opt.step()
+        with torch.no_grad():
+            p.clamp_(clamp[0], clamp[1])
+    return float(p.detach()), hist

@@ -1,0 +1,429 @@
+// C ABI of libidw.so: argument validation, workspace carving, launch configuration and
+// dispatch to the per-layout kernel translation units.  No entry point here allocates
+// device memory or synchronises.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/idw.h"
+#include "idw_api_internal.hpp"
+#include "idw_launch.hpp"
+
+namespace idw {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return IDW_OK;
+  return fail(IDW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- device check: the code objects are built for gfx950 only ----
+int check_device() {
+  static std::mutex mu;
+  static int state[64] = {0};  // 0 unknown, 1 ok, 2 bad
+  int dev = 0;
+  int cnt = 0;
+  if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0)
+    return fail(IDW_EDEVICE, "no HIP device available");
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    return fail(IDW_EDEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  if (state[dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+      return fail(IDW_EDEVICE, "hipGetDeviceProperties failed");
+    state[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+  }
+  if (state[dev] != 1) return fail(IDW_EDEVICE, "device %d is not gfx950", dev);
+  return IDW_OK;
+}
+
+// ---- validation ----
+static size_t elem(int precision) { return precision == IDW_FP64 ? 8 : 4; }
+
+int record_bytes(int layout, int dim, int precision, bool is_data, size_t b[4]) {
+  for (int k = 0; k < 4; ++k) b[k] = 0;
+  if (dim != 2 && dim != 3) return fail(IDW_EINVAL, "dim must be 2 or 3 (got %d)", dim);
+  if (precision != IDW_FP32 && precision != IDW_FP64)
+    return fail(IDW_EINVAL, "unknown precision %d", precision);
+  const size_t e = elem(precision);
+  switch (layout) {
+    case IDW_SOA:
+      for (int k = 0; k < dim; ++k) b[k] = e;
+      if (is_data) b[dim] = e;
+      break;
+    case IDW_AOS:
+      b[0] = e * (dim + (is_data ? 1 : 0));
+      break;
+    case IDW_AOAS:
+      b[0] = 4 * e;
+      break;
+    case IDW_HYBRID:
+      b[0] = e * dim;
+      if (is_data) b[1] = e;
+      break;
+    case IDW_SOAOS:
+      b[0] = e * (dim == 2 ? 2 : 4);
+      if (is_data) b[1] = 2 * e;
+      break;
+    default:
+      return fail(IDW_EINVAL, "unknown layout %d", layout);
+  }
+  return IDW_OK;
+}
+
+// Required alignment of slot k: the record size for the aligned layouts, else the element.
+static size_t slot_align(int layout, int precision, const size_t b[4], int k) {
+  if (layout == IDW_AOAS || layout == IDW_SOAOS) return b[k];
+  return elem(precision);
+}
+
+int validate_points(const idw_points* P, int precision, bool is_data, const char* what) {
+  if (!P) return fail(IDW_EINVAL, "%s: null descriptor", what);
+  if (P->n < 0) return fail(IDW_EINVAL, "%s: negative count", what);
+  if (is_data && P->n < 1) return fail(IDW_EINVAL, "%s: at least one data point is required", what);
+  if (P->n > 0x7fffffffLL) return fail(IDW_EINVAL, "%s: count above 2^31-1", what);
+  size_t b[4];
+  int rc = record_bytes(P->layout, P->dim, precision, is_data, b);
+  if (rc != IDW_OK) {
+    std::string m = g_err;
+    return fail(rc, "%s: %s", what, m.c_str());
+  }
+  if (P->n == 0) return IDW_OK;
+  for (int k = 0; k < 4; ++k) {
+    if (!b[k]) continue;
+    if (!P->ptr[k]) return fail(IDW_EINVAL, "%s: pointer slot %d is null", what, k);
+    const size_t al = slot_align(P->layout, precision, b, k);
+    if (reinterpret_cast<uintptr_t>(P->ptr[k]) % al)
+      return fail(IDW_EINVAL, "%s: pointer slot %d is not %zu-byte aligned", what, k, al);
+  }
+  return IDW_OK;
+}
+
+static bool same_query_layout(int a, int b) {
+  auto canon = [](int l) { return l == IDW_HYBRID ? IDW_AOS : l; };
+  return canon(a) == canon(b);
+}
+
+int validate_common(const idw_points* data, const idw_points* query, double p, int precision,
+                    uint32_t flags) {
+  if (precision != IDW_FP32 && precision != IDW_FP64)
+    return fail(IDW_EINVAL, "unknown precision %d", precision);
+  int rc = validate_points(data, precision, true, "data");
+  if (rc) return rc;
+  rc = validate_points(query, precision, false, "query");
+  if (rc) return rc;
+  if (data->dim != query->dim) return fail(IDW_EINVAL, "data and query dims differ");
+  if (!same_query_layout(data->layout, query->layout))
+    return fail(IDW_EUNSUPPORTED, "query layout must match the data layout (AoS and hybrid "
+                                  "query records are the same)");
+  if (!(p > 0.0) || !(p <= 64.0)) return fail(IDW_EINVAL, "p must satisfy 0 < p <= 64");
+  if (flags & ~(IDW_EXCLUDE_SELF | IDW_NEED_DZ | IDW_NEED_DP | IDW_NEED_DQ))
+    return fail(IDW_EINVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & IDW_EXCLUDE_SELF) && query->n != data->n)
+    return fail(IDW_EINVAL, "IDW_EXCLUDE_SELF needs as many queries as data points");
+  return IDW_OK;
+}
+
+int pmode_of(double p) {
+  if (p == 1.0) return PM_1;
+  if (p == 2.0) return PM_2;
+  if (p == 3.0) return PM_3;
+  if (p == 4.0) return PM_4;
+  if (p == 2.5) return PM_25;
+  return PM_GEN;
+}
+
+// ---- launch configuration and workspace layout ----
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Splits `len` points into chunks (multiples of the tile) so that `blocks` x chunks fills
+// the chip (about 2 workgroups per compute unit), with at least 4 tiles per chunk.
+static void choose_split(int64_t len, int64_t blocks, int want_split, int& split, int64_t& chunk) {
+  int s = want_split;
+  if (s <= 0) {
+    const int64_t target = 512;
+    s = static_cast<int>(cdiv(target, blocks > 0 ? blocks : 1));
+    const int64_t maxs = cdiv(len, 4 * kTile);
+    if (s > maxs) s = static_cast<int>(maxs);
+  }
+  if (s < 1) s = 1;
+  if (s > 1024) s = 1024;
+  chunk = cdiv(cdiv(len, s), kTile) * kTile;
+  split = static_cast<int>(cdiv(len, chunk));
+}
+
+WsPlan plan_workspace(const idw_points* data, const idw_points* query, int precision,
+                      const idw_config* cfg) {
+  WsPlan w;
+  const bool f64 = precision == IDW_FP64;
+  const int64_t n = data->n, m = query->n;
+  // forward
+  w.qf = (cfg && cfg->queries_per_lane) ? cfg->queries_per_lane : (f64 ? 4 : 8);
+  choose_split(n, cdiv(m, kWG * w.qf), cfg ? cfg->split : 0, w.split_f, w.chunk_f);
+  // backward: query sweep over data chunks, data sweep over query chunks
+  w.qq = f64 ? 2 : 4;
+  choose_split(n, cdiv(m, kWG * w.qq), 0, w.split_q, w.chunk_q);
+  w.qz = f64 ? 2 : 8;
+  choose_split(m > 0 ? m : 1, cdiv(n, kWG * w.qz), 0, w.split_z, w.chunk_z);
+  w.nbbox = static_cast<int>(std::min<int64_t>(1024, cdiv(n, kWG)));
+  w.nwg_dp = static_cast<int>(cdiv(m, kWG));
+  const int64_t nb = cdiv(m > 0 ? m : 1, kCountBlock);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = al256(off + bytes);
+    return at;
+  };
+  w.hdr = take(512);
+  w.bbox = take(sizeof(double) * 6 * static_cast<size_t>(w.nbbox));
+  w.flag = take(static_cast<size_t>(m));
+  w.bcnt = take(sizeof(int) * static_cast<size_t>(nb + 1));
+  w.list = take(sizeof(int) * static_cast<size_t>(m));
+  w.part_f = take(w.split_f > 1 ? sizeof(double2) * static_cast<size_t>(w.split_f) * m : 0);
+  w.part_q = take(sizeof(double4) * static_cast<size_t>(w.split_q) * m);
+  w.part_z = take(sizeof(double) * static_cast<size_t>(w.split_z) * n);
+  w.slot_coef = take(sizeof(double) * static_cast<size_t>(m));
+  w.slot_hits = take(sizeof(int) * static_cast<size_t>(m));
+  w.slot_dp = take(sizeof(double) * static_cast<size_t>(m));
+  w.wg_dp = take(sizeof(double) * static_cast<size_t>(w.nwg_dp > 0 ? w.nwg_dp : 1));
+  w.total = off;
+  (void)f64;
+  return w;
+}
+
+// ---- per-layout dispatch tables ----
+struct LayoutFns {
+  hipError_t (*fwd_sweep)(const FwdArgs&, bool, hipStream_t);
+  hipError_t (*fwd_fixup)(const FwdArgs&, bool, hipStream_t);
+  hipError_t (*bbox)(const DevPts&, int64_t, int, bool, double*, int, hipStream_t);
+  hipError_t (*bwd_query)(const BwdArgs&, bool, hipStream_t);
+  hipError_t (*bwd_data)(const BwdArgs&, bool, hipStream_t);
+  hipError_t (*bwd_fixup)(const BwdArgs&, bool, hipStream_t);
+};
+
+static const LayoutFns kFns[5] = {
+    {fwd_sweep_soa, fwd_fixup_soa, bbox_soa, bwd_query_soa, bwd_data_soa, bwd_fixup_soa},
+    {fwd_sweep_aos, fwd_fixup_aos, bbox_aos, bwd_query_aos, bwd_data_aos, bwd_fixup_aos},
+    {fwd_sweep_aoas, fwd_fixup_aoas, bbox_aoas, bwd_query_aoas, bwd_data_aoas, bwd_fixup_aoas},
+    {fwd_sweep_hybrid, fwd_fixup_hybrid, bbox_hybrid, bwd_query_hybrid, bwd_data_hybrid,
+     bwd_fixup_hybrid},
+    {fwd_sweep_soaos, fwd_fixup_soaos, bbox_soaos, bwd_query_soaos, bwd_data_soaos,
+     bwd_fixup_soaos},
+};
+
+const LayoutFns& fns(int layout) { return kFns[layout]; }
+
+DevPts dev_pts(const idw_points* P) {
+  DevPts d;
+  for (int k = 0; k < 4; ++k) d.p[k] = P->ptr[k];
+  return d;
+}
+
+int check_workspace(void* ws, size_t bytes, size_t need) {
+  if (!ws) return fail(IDW_EWORKSPACE, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(IDW_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < need) return fail(IDW_EWORKSPACE, "workspace too small: %zu < %zu bytes", bytes, need);
+  return IDW_OK;
+}
+
+// Enqueues the extent/threshold header computation.
+hipError_t enqueue_header(const idw_points* data, double p, bool f64, char* ws, const WsPlan& w,
+                          hipStream_t st) {
+  hipError_t e = fns(data->layout).bbox(dev_pts(data), data->n, data->dim, f64,
+                                        reinterpret_cast<double*>(ws + w.bbox), w.nbbox, st);
+  if (e != hipSuccess) return e;
+  return bbox_final(reinterpret_cast<double*>(ws + w.bbox), w.nbbox, data->dim, p, !f64,
+                    reinterpret_cast<double*>(ws + w.hdr), st);
+}
+
+}  // namespace idw
+
+using namespace idw;
+
+extern "C" {
+
+const char* idw_version(void) { return "idw-gfx950 0.1.0"; }
+
+const char* idw_last_error(void) { return g_err.c_str(); }
+
+int idw_record_bytes(int32_t layout, int32_t dim, int32_t precision, int32_t is_data,
+                     size_t bytes[4]) {
+  clear_error();
+  if (!bytes) return fail(IDW_EINVAL, "bytes is null");
+  return record_bytes(layout, dim, precision, is_data != 0, bytes);
+}
+
+int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t precision,
+                       const idw_config* cfg, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(IDW_EINVAL, "bytes is null");
+  int rc = validate_common(data, query, 2.0, precision, 0);
+  if (rc) return rc;
+  *bytes = plan_workspace(data, query, precision, cfg).total;
+  return IDW_OK;
+}
+
+int idw_forward(const idw_points* data, const idw_points* query, double p, int32_t precision,
+                uint32_t flags, void* out_z, double* out_den, void* workspace,
+                size_t workspace_bytes, void* stream, const idw_config* cfg) {
+  clear_error();
+  int rc = validate_common(data, query, p, precision, flags);
+  if (rc) return rc;
+  if (flags & ~IDW_EXCLUDE_SELF) return fail(IDW_EINVAL, "idw_forward accepts only IDW_EXCLUDE_SELF");
+  if (cfg && cfg->queries_per_lane) {
+    const int q = cfg->queries_per_lane;
+    const bool ok = precision == IDW_FP64 ? (q == 2 || q == 4) : (q == 4 || q == 8);
+    if (!ok) return fail(IDW_EUNSUPPORTED, "queries_per_lane %d not built for this precision", q);
+  }
+  if (cfg && (cfg->split < 0 || cfg->split > 1024)) return fail(IDW_EINVAL, "split must be in 0..1024");
+  const int64_t m = query->n;
+  if (m == 0) return IDW_OK;
+  if (!out_z) return fail(IDW_EINVAL, "out_z is null");
+  const WsPlan w = plan_workspace(data, query, precision, cfg);
+  rc = check_workspace(workspace, workspace_bytes, w.total);
+  if (rc) return rc;
+  rc = check_device();
+  if (rc) return rc;
+  const bool f64 = precision == IDW_FP64;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+
+  FwdArgs a;
+  a.data = dev_pts(data);
+  a.n = data->n;
+  a.query = dev_pts(query);
+  a.m = m;
+  a.dim = data->dim;
+  a.pmode = pmode_of(p);
+  a.p = p;
+  a.flags = flags;
+  a.q_per_lane = w.qf;
+  a.split = w.split_f;
+  a.chunk = w.chunk_f;
+  a.hdr = reinterpret_cast<const double*>(ws + w.hdr);
+  a.out_z = out_z;
+  a.out_den = out_den;
+  a.flag = reinterpret_cast<uint8_t*>(ws + w.flag);
+  a.part = reinterpret_cast<double2*>(ws + w.part_f);
+  a.list = reinterpret_cast<const int*>(ws + w.list);
+  a.count = reinterpret_cast<const int*>(ws + w.hdr + 256);
+
+  const LayoutFns& F = fns(data->layout);
+  if ((rc = check_hip(enqueue_header(data, p, f64, ws, w, st), "extent kernels"))) return rc;
+  if ((rc = check_hip(F.fwd_sweep(a, f64, st), "forward sweep"))) return rc;
+  if (a.split > 1 &&
+      (rc = check_hip(merge_split(a.part, m, a.split, a.hdr, out_z, f64, out_den, a.flag, st), "merge")))
+    return rc;
+  if ((rc = check_hip(compact_flags(a.flag, m, reinterpret_cast<int*>(ws + w.bcnt),
+                                    reinterpret_cast<int*>(ws + w.list),
+                                    reinterpret_cast<int*>(ws + w.hdr + 256), st),
+                      "compaction")))
+    return rc;
+  if ((rc = check_hip(F.fwd_fixup(a, f64, st), "FP64 fix-up"))) return rc;
+  return IDW_OK;
+}
+
+int idw_backward(const idw_points* data, const idw_points* query, double p, int32_t precision,
+                 uint32_t flags, const void* grad_out, const void* saved_z,
+                 const double* saved_den, void* grad_z, double* grad_p, void* grad_q,
+                 void* workspace, size_t workspace_bytes, void* stream, const idw_config* cfg) {
+  clear_error();
+  int rc = validate_common(data, query, p, precision, flags);
+  if (rc) return rc;
+  const bool ndz = flags & IDW_NEED_DZ, ndp = flags & IDW_NEED_DP, ndq = flags & IDW_NEED_DQ;
+  if (!(ndz || ndp || ndq)) return fail(IDW_EINVAL, "no gradient requested (IDW_NEED_* flags)");
+  if (ndz && !grad_z) return fail(IDW_EINVAL, "IDW_NEED_DZ set but grad_z is null");
+  if (ndp && !grad_p) return fail(IDW_EINVAL, "IDW_NEED_DP set but grad_p is null");
+  if (ndq && !grad_q && query->n > 0) return fail(IDW_EINVAL, "IDW_NEED_DQ set but grad_q is null");
+  const int64_t m = query->n;
+  if (m > 0 && (!grad_out || !saved_z || !saved_den))
+    return fail(IDW_EINVAL, "grad_out, saved_z and saved_den are required");
+  const WsPlan w = plan_workspace(data, query, precision, cfg);
+  rc = check_workspace(workspace, workspace_bytes, w.total);
+  if (rc) return rc;
+  rc = check_device();
+  if (rc) return rc;
+  const bool f64 = precision == IDW_FP64;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  if (m == 0) {  // no queries: every gradient is zero
+    if (ndz && (rc = check_hip(fill_zero(grad_z, static_cast<size_t>(data->n) * elem(precision), st), "fill")))
+      return rc;
+    if (ndp && (rc = check_hip(fill_zero(grad_p, sizeof(double), st), "fill"))) return rc;
+    return IDW_OK;
+  }
+
+  BwdArgs a;
+  a.data = dev_pts(data);
+  a.n = data->n;
+  a.query = dev_pts(query);
+  a.m = m;
+  a.dim = data->dim;
+  a.pmode = pmode_of(p);
+  a.p = p;
+  a.flags = flags & (IDW_EXCLUDE_SELF | (ndp ? IDW_NEED_DP : 0u) | (ndq ? IDW_NEED_DQ : 0u));
+  a.q_per_lane = w.qq;
+  a.x_per_lane = w.qz;
+  a.split_q = w.split_q;
+  a.chunk_q = w.chunk_q;
+  a.split_z = w.split_z;
+  a.chunk_z = w.chunk_z;
+  a.part_q = reinterpret_cast<double4*>(ws + w.part_q);
+  a.part_z = reinterpret_cast<double*>(ws + w.part_z);
+  a.hdr = reinterpret_cast<const double*>(ws + w.hdr);
+  a.grad_out = grad_out;
+  a.saved_z = saved_z;
+  a.saved_den = saved_den;
+  a.grad_z = ndz ? grad_z : nullptr;
+  a.grad_q = ndq ? grad_q : nullptr;
+  a.wg_dp = ndp ? reinterpret_cast<double*>(ws + w.wg_dp) : nullptr;
+  a.list = reinterpret_cast<const int*>(ws + w.list);
+  a.count = reinterpret_cast<const int*>(ws + w.hdr + 256);
+  a.slot_coef = reinterpret_cast<double*>(ws + w.slot_coef);
+  a.slot_hits = reinterpret_cast<int*>(ws + w.slot_hits);
+  a.slot_dp = reinterpret_cast<double*>(ws + w.slot_dp);
+
+  const LayoutFns& F = fns(data->layout);
+  uint8_t* flag = reinterpret_cast<uint8_t*>(ws + w.flag);
+  if ((rc = check_hip(enqueue_header(data, p, f64, ws, w, st), "extent kernels"))) return rc;
+  if ((rc = check_hip(flags_from_den(saved_den, m, a.hdr, flag, st), "flags"))) return rc;
+  if ((rc = check_hip(compact_flags(flag, m, reinterpret_cast<int*>(ws + w.bcnt),
+                                    reinterpret_cast<int*>(ws + w.list),
+                                    reinterpret_cast<int*>(ws + w.hdr + 256), st),
+                      "compaction")))
+    return rc;
+  if (ndp || ndq) {
+    if ((rc = check_hip(F.bwd_query(a, f64, st), "query sweep"))) return rc;
+    if ((rc = check_hip(bwd_qmerge(a, f64, st), "query merge"))) return rc;
+  }
+  if (ndz) {
+    if ((rc = check_hip(F.bwd_data(a, f64, st), "data sweep"))) return rc;
+    if ((rc = check_hip(bwd_zmerge(a, f64, st), "data merge"))) return rc;
+  }
+  if ((rc = check_hip(F.bwd_fixup(a, f64, st), "FP64 fix-up"))) return rc;
+  if (ndp && (rc = check_hip(dp_final(a.wg_dp, w.nwg_dp, a.slot_dp, a.count, grad_p, st), "dp reduction")))
+    return rc;
+  return IDW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,630 @@
+// Adjoint of the IDW forward sweep (Eq. 1 differentiated with respect to z, p and q).
+//
+// For a query i that is not flagged (no data point within 1e-6 of the extent):
+//   dZ_i/dz_j = w_ij / D_i
+//   dZ_i/dp   = -(1/D_i) sum_j w_ij (1/2) ln(r2_ij) (z_j - Z_i)
+//   dZ_i/dq_i = -(p/D_i) sum_j (w_ij / r2_ij) (z_j - Z_i) (q_i - x_j)
+// The centred factor (z_j - Z_i) keeps the p and q sums free of the cancellation of
+// sum w ln(r2) z - Z sum w ln(r2).
+//
+// Three sweeps:
+//  * query sweep: lanes own queries, data tiles broadcast from LDS; accumulates
+//    P_i = sum w (z - Z) log2(r2) and G_i = sum (w/r2)(z - Z)(q - x) with blocked TwoSum;
+//    writes per-(data chunk, query) partials that a merge kernel turns into dq_i and
+//    per-workgroup dp partials in a fixed order;
+//  * data sweep: lanes own data points, query tiles (q_i, a_i = g_i / D_i) broadcast from
+//    LDS; accumulates dz_j = sum_i a_i w_ij;
+//  * FP64 fix-up for flagged queries (exact hits and near-coincident points): a per-query
+//    workgroup recomputes Z, D, dq and dp exactly, and a data-parallel pass adds their dz
+//    contributions in ascending query order.
+#pragma once
+
+#include <math.h>
+
+#include "idw_device.hpp"
+#include "idw_fwd.hpp"
+#include "idw_launch.hpp"
+
+namespace idw {
+
+// w and, when needed, w / r2 and log2(r2), in the cheapest form for the weight class.
+template <int PM, bool NDQ, bool NDP>
+__device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& wr, float& lg) {
+  if constexpr (PM == PM_GEN) {
+    lg = __builtin_amdgcn_logf(r2);
+    w = __builtin_amdgcn_exp2f(nhp * lg);
+    if constexpr (NDQ) wr = w * __builtin_amdgcn_rcpf(r2);
+  } else {
+    if constexpr (NDP) lg = __builtin_amdgcn_logf(r2);
+    if constexpr (PM == PM_2) {
+      w = __builtin_amdgcn_rcpf(r2);
+      if constexpr (NDQ) wr = w * w;
+    } else if constexpr (PM == PM_1) {
+      w = __builtin_amdgcn_rsqf(r2);
+      if constexpr (NDQ) wr = w * w * w;
+    } else if constexpr (PM == PM_3) {
+      const float s = __builtin_amdgcn_rsqf(r2);
+      const float s2 = s * s;
+      w = s2 * s;
+      if constexpr (NDQ) wr = w * s2;
+    } else if constexpr (PM == PM_4) {
+      const float t = __builtin_amdgcn_rcpf(r2);
+      w = t * t;
+      if constexpr (NDQ) wr = w * t;
+    } else {  // PM_25
+      const float s = __builtin_amdgcn_rsqf(r2);
+      const float s2 = s * s;
+      w = s2 * __builtin_amdgcn_sqrtf(s);
+      if constexpr (NDQ) wr = w * s2;
+    }
+  }
+}
+
+template <int PM, bool NDQ, bool NDP>
+__device__ __forceinline__ void wterms(double r2, double nhp, double& w, double& wr, double& lg) {
+  if constexpr (NDP || PM == PM_GEN) lg = log2(r2);
+  if constexpr (PM == PM_GEN)
+    w = exp2(nhp * lg);
+  else
+    w = weight<PM>(r2, nhp);
+  if constexpr (NDQ) wr = w / r2;
+}
+
+// One LDS tile of the query sweep.  `cnt` records are valid (all of them unless TAIL).
+template <typename T, int DIM, int PM, int Q, bool DIAG, bool TAIL, bool NDP, bool NDQ>
+__device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt, int64_t jt,
+                                          const T (&qc)[Q][3], const T (&zq)[Q],
+                                          const int64_t (&qi)[Q], T nhp, T (&ph)[Q], T (&pl)[Q],
+                                          T (&gh)[Q][3], T (&gl)[Q][3]) {
+  constexpr int CH = 64;
+  const int lim = TAIL ? cnt : kTile;
+  for (int c0 = 0; c0 < lim; c0 += CH) {
+    T ap[Q], ag[Q][3];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      ap[k] = T(0);
+      ag[k][0] = ag[k][1] = ag[k][2] = T(0);
+    }
+    const int ce = TAIL ? ((lim - c0) < CH ? (lim - c0) : CH) : CH;
+#pragma unroll 2
+    for (int jj = 0; jj < ce; ++jj) {
+      const P4<T> d = tl[c0 + jj];
+      const T dv = (DIM == 3) ? d.w : d.z;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const T dx = qc[k][0] - d.x;
+        const T dy = qc[k][1] - d.y;
+        T dz = T(0);
+        T r2 = dx * dx;
+        r2 = fmaT(dy, dy, r2);
+        if constexpr (DIM == 3) {
+          dz = qc[k][2] - d.z;
+          r2 = fmaT(dz, dz, r2);
+        }
+        T c = dv - zq[k];
+        if constexpr (DIAG) {
+          if (jt + c0 + jj == qi[k]) {
+            r2 = T(1);
+            c = T(0);
+          }
+        }
+        T w, wr = T(0), lg = T(0);
+        wterms<PM, NDQ, NDP>(r2, nhp, w, wr, lg);
+        if constexpr (NDP) ap[k] = fmaT(w * c, lg, ap[k]);
+        if constexpr (NDQ) {
+          const T u = c * wr;
+          ag[k][0] = fmaT(u, dx, ag[k][0]);
+          ag[k][1] = fmaT(u, dy, ag[k][1]);
+          if constexpr (DIM == 3) ag[k][2] = fmaT(u, dz, ag[k][2]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if constexpr (NDP) two_sum_acc(ph[k], pl[k], ap[k]);
+      if constexpr (NDQ) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) two_sum_acc(gh[k][d], gl[k][d], ag[k][d]);
+      }
+    }
+  }
+}
+
+// Query sweep: writes part[c * m + i] = (P, Gx, Gy, Gz) in scaled units (double).
+template <typename T, int DIM, int L, int PM, int Q, bool NDP, bool NDQ>
+__global__ __launch_bounds__(kWG) void k_bwd_query(DevPts data, int64_t n, DevPts query, int64_t m,
+                                                   int64_t chunk, T nhp, unsigned flags,
+                                                   const double* __restrict__ hdr,
+                                                   const T* __restrict__ saved_z,
+                                                   double4* __restrict__ part) {
+  __shared__ P4<T> tile[2][kTile];
+  const int tid = threadIdx.x;
+  const int64_t q0 = static_cast<int64_t>(blockIdx.x) * (kWG * Q);
+  const int64_t jb = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t je = (jb + chunk < n) ? jb + chunk : n;
+  const T s = static_cast<T>(hdr[H_SCALE]);
+
+  T qc[Q][3], zq[Q];
+  int64_t qi[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    qi[k] = q0 + tid + static_cast<int64_t>(k) * kWG;
+    T c[3] = {T(0), T(0), T(0)};
+    zq[k] = T(0);
+    if (qi[k] < m) {
+      Loader<T, DIM, L>::query(query, qi[k], c);
+      zq[k] = saved_z[qi[k]];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) qc[k][d] = c[d] * s;
+  }
+  T ph[Q], pl[Q], gh[Q][3], gl[Q][3];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    ph[k] = pl[k] = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gh[k][d] = gl[k][d] = T(0);
+  }
+
+  T rc[2][3], rv[2];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t j = jb + static_cast<int64_t>(t) * kTile + u * kWG + tid;
+      rc[u][0] = rc[u][1] = rc[u][2] = T(0);
+      rv[u] = T(0);
+      if (j < je) Loader<T, DIM, L>::data(data, j, rc[u], rv[u]);
+    }
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) tile[b][u * kWG + tid] = stage<T, DIM>(rc[u], rv[u], s);
+  };
+
+  const int ntiles = static_cast<int>((je - jb + kTile - 1) / kTile);
+  const bool excl = (flags & 1u) != 0;
+  fetch(0);
+  put(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) fetch(t + 1);
+    const int64_t jt = jb + static_cast<int64_t>(t) * kTile;
+    const int cnt = static_cast<int>((je - jt) < kTile ? (je - jt) : kTile);
+    const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
+    if (cnt < kTile) {
+      if (diag)
+        bwdq_tile<T, DIM, PM, Q, true, true, NDP, NDQ>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+      else
+        bwdq_tile<T, DIM, PM, Q, false, true, NDP, NDQ>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+    } else {
+      if (diag)
+        bwdq_tile<T, DIM, PM, Q, true, false, NDP, NDQ>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+      else
+        bwdq_tile<T, DIM, PM, Q, false, false, NDP, NDQ>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+    }
+    if (t + 1 < ntiles) put((t + 1) & 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (qi[k] < m) {
+      double4 r;
+      r.x = static_cast<double>(ph[k]) + static_cast<double>(pl[k]);
+      r.y = static_cast<double>(gh[k][0]) + static_cast<double>(gl[k][0]);
+      r.z = static_cast<double>(gh[k][1]) + static_cast<double>(gl[k][1]);
+      r.w = static_cast<double>(gh[k][2]) + static_cast<double>(gl[k][2]);
+      part[static_cast<int64_t>(blockIdx.y) * m + qi[k]] = r;
+    }
+  }
+}
+
+// Merges query-sweep partials: dq_i for unflagged queries, dp partial per workgroup.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kWG) void k_bwd_qmerge(const double4* __restrict__ part, int64_t m,
+                                                    int split, double p,
+                                                    const double* __restrict__ hdr,
+                                                    const T* __restrict__ grad_out,
+                                                    const double* __restrict__ saved_den,
+                                                    T* __restrict__ grad_q,
+                                                    double* __restrict__ wg_dp) {
+  __shared__ double red[kWG];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  double dpi = 0.0;
+  if (i < m) {
+    const double D = saved_den[i];
+    const bool ok = D <= hdr[H_THR_U] && D > hdr[H_LO_U];
+    if (ok) {
+      double P[2] = {0.0, 0.0}, G[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+      for (int c = 0; c < split; ++c) {
+        const double4 v = part[static_cast<int64_t>(c) * m + i];
+        two_sum_acc(P[0], P[1], v.x);
+        two_sum_acc(G[0][0], G[0][1], v.y);
+        two_sum_acc(G[1][0], G[1][1], v.z);
+        two_sum_acc(G[2][0], G[2][1], v.w);
+      }
+      const double Ds = D / hdr[H_DEN_UNIT];  // denominator in the sweep's scaled units
+      const double g = static_cast<double>(grad_out[i]);
+      // ln(r2) = log2(r2) * ln 2; dZ/dp = -(1/D) sum w (1/2) ln(r2) (z - Z).
+      dpi = -(g / Ds) * 0.5 * 0.69314718055994530942 * (P[0] + P[1]);
+      if (grad_q) {
+        const double f = -(p * g / Ds) * hdr[H_SCALE];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) grad_q[i * DIM + d] = static_cast<T>(f * (G[d][0] + G[d][1]));
+      }
+    }
+  }
+  const double tot = block_sum(dpi, red);
+  if (threadIdx.x == 0 && wg_dp) wg_dp[blockIdx.x] = tot;
+}
+
+// One LDS tile of the data sweep: for the lane's Q data points, accumulate a_i * w_ij.
+template <typename T, int DIM, int PM, int Q, bool DIAG>
+__device__ __forceinline__ void bwdd_tile(const P4<T>* __restrict__ tl, int64_t it,
+                                          const T (&xc)[Q][3], const int64_t (&xj)[Q], T nhp,
+                                          T (&zh)[Q], T (&zl)[Q]) {
+  constexpr int CH = 64;
+  for (int c0 = 0; c0 < kTile; c0 += CH) {
+    T az[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) az[k] = T(0);
+#pragma unroll 4
+    for (int ii = 0; ii < CH; ++ii) {
+      const P4<T> d = tl[c0 + ii];
+      const T a = (DIM == 3) ? d.w : d.z;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const T r2 = sqdist<T, DIM>(xc[k], d);
+        T w = weight<PM>(r2, nhp);
+        if constexpr (DIAG) {
+          if (it + c0 + ii == xj[k]) w = T(0);
+        }
+        az[k] = fmaT(a, w, az[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) two_sum_acc(zh[k], zl[k], az[k]);
+  }
+}
+
+// Data sweep: part[c * n + j] = sum over query chunk c of a_i w_ij (double).
+template <typename T, int DIM, int L, int PM, int Q>
+__global__ __launch_bounds__(kWG) void k_bwd_data(DevPts data, int64_t n, DevPts query, int64_t m,
+                                                  int64_t chunk, T nhp, unsigned flags,
+                                                  const double* __restrict__ hdr,
+                                                  const T* __restrict__ grad_out,
+                                                  const double* __restrict__ saved_den,
+                                                  double* __restrict__ part) {
+  __shared__ P4<T> tile[2][kTile];
+  const int tid = threadIdx.x;
+  const int64_t x0 = static_cast<int64_t>(blockIdx.x) * (kWG * Q);
+  const int64_t ib = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t ie = (ib + chunk < m) ? ib + chunk : m;
+  const T s = static_cast<T>(hdr[H_SCALE]);
+  const double thr = hdr[H_THR_U], lo = hdr[H_LO_U], unit = hdr[H_DEN_UNIT];
+
+  T xc[Q][3];
+  int64_t xj[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    xj[k] = x0 + tid + static_cast<int64_t>(k) * kWG;
+    T c[3] = {T(0), T(0), T(0)}, v = T(0);
+    if (xj[k] < n) Loader<T, DIM, L>::data(data, xj[k], c, v);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xc[k][d] = c[d] * s;
+  }
+  T zh[Q], zl[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) zh[k] = zl[k] = T(0);
+
+  T rc[2][3], ra[2];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t i = ib + static_cast<int64_t>(t) * kTile + u * kWG + tid;
+      rc[u][0] = rc[u][1] = rc[u][2] = infT<T>();
+      ra[u] = T(0);
+      if (i < ie) {
+        const double D = saved_den[i];
+        if (D <= thr && D > lo) {  // flagged queries are left to the FP64 fix-up
+          T c[3] = {T(0), T(0), T(0)};
+          Loader<T, DIM, L>::query(query, i, c);
+          rc[u][0] = c[0];
+          rc[u][1] = c[1];
+          rc[u][2] = c[2];
+          ra[u] = static_cast<T>(static_cast<double>(grad_out[i]) / (D / unit));
+        }
+      }
+    }
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) tile[b][u * kWG + tid] = stage<T, DIM>(rc[u], ra[u], s);
+  };
+
+  const int ntiles = static_cast<int>((ie - ib + kTile - 1) / kTile);
+  const bool excl = (flags & 1u) != 0;
+  fetch(0);
+  put(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) fetch(t + 1);
+    const int64_t it = ib + static_cast<int64_t>(t) * kTile;
+    const bool diag = excl && it < x0 + kWG * Q && x0 < it + kTile;
+    if (diag)
+      bwdd_tile<T, DIM, PM, Q, true>(tile[t & 1], it, xc, xj, nhp, zh, zl);
+    else
+      bwdd_tile<T, DIM, PM, Q, false>(tile[t & 1], it, xc, xj, nhp, zh, zl);
+    if (t + 1 < ntiles) put((t + 1) & 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    if (xj[k] < n)
+      part[static_cast<int64_t>(blockIdx.y) * n + xj[k]] =
+          static_cast<double>(zh[k]) + static_cast<double>(zl[k]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_bwd_zmerge(const double* __restrict__ part, int64_t n,
+                                                    int split, T* __restrict__ grad_z) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (j >= n) return;
+  double h = 0.0, l = 0.0;
+  for (int c = 0; c < split; ++c) two_sum_acc(h, l, part[static_cast<int64_t>(c) * n + j]);
+  grad_z[j] = static_cast<T>(h + l);
+}
+
+// FP64 per-query fix-up of the adjoint for flagged queries (one workgroup per query).
+template <typename T, int DIM, int L, int PM>
+__global__ __launch_bounds__(kWG) void k_bwd_fixq(DevPts data, int64_t n, DevPts query, double p,
+                                                  unsigned flags, const int* __restrict__ list,
+                                                  const int* __restrict__ count,
+                                                  const T* __restrict__ grad_out,
+                                                  T* __restrict__ grad_q,
+                                                  double* __restrict__ slot_coef,
+                                                  int* __restrict__ slot_hits,
+                                                  double* __restrict__ slot_dp) {
+  __shared__ double red[kWG];
+  __shared__ long long redi[kWG];
+  const int cnt = *count;
+  const bool excl = (flags & 1u) != 0;
+  const double nhp = -0.5 * p;
+  for (int sl = blockIdx.x; sl < cnt; sl += gridDim.x) {
+    const int64_t i = list[sl];
+    T qt[3] = {T(0), T(0), T(0)};
+    Loader<T, DIM, L>::query(query, i, qt);
+    double q[3] = {static_cast<double>(qt[0]), static_cast<double>(qt[1]), static_cast<double>(qt[2])};
+    NSum num, den;
+    long long h = 0;
+    for (int64_t j = threadIdx.x; j < n; j += kWG) {
+      if (excl && j == i) continue;
+      T c[3] = {T(0), T(0), T(0)}, v;
+      Loader<T, DIM, L>::data(data, j, c, v);
+      double r2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double e = q[d] - static_cast<double>(c[d]);
+        r2 += e * e;
+      }
+      if (r2 == 0.0) {
+        ++h;
+      } else {
+        const double w = weight<PM>(r2, nhp);
+        num.add(w * static_cast<double>(v));
+        den.add(w);
+      }
+    }
+    const double tn = block_sum(num.value(), red);
+    const double td = block_sum(den.value(), red);
+    const long long th = block_sum_i64(h, redi);
+    const double g = static_cast<double>(grad_out[i]);
+    if (th > 0) {
+      if (threadIdx.x == 0) {
+        slot_coef[sl] = g / static_cast<double>(th);
+        slot_hits[sl] = static_cast<int>(th);
+        slot_dp[sl] = 0.0;
+        if (grad_q)
+          for (int d = 0; d < DIM; ++d) grad_q[i * DIM + d] = T(0);
+      }
+      continue;
+    }
+    const double Z = tn / td;
+    NSum P, G[3];
+    for (int64_t j = threadIdx.x; j < n; j += kWG) {
+      if (excl && j == i) continue;
+      T c[3] = {T(0), T(0), T(0)}, v;
+      Loader<T, DIM, L>::data(data, j, c, v);
+      double e[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        e[d] = q[d] - static_cast<double>(c[d]);
+        r2 += e[d] * e[d];
+      }
+      const double w = weight<PM>(r2, nhp);
+      const double cz = static_cast<double>(v) - Z;
+      P.add(w * 0.5 * log(r2) * cz);
+      const double u = (w / r2) * cz;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) G[d].add(u * e[d]);
+    }
+    const double tP = block_sum(P.value(), red);
+    double tG[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < DIM; ++d) tG[d] = block_sum(G[d].value(), red);
+    if (threadIdx.x == 0) {
+      slot_coef[sl] = g / td;
+      slot_hits[sl] = 0;
+      slot_dp[sl] = -(g / td) * tP;
+      if (grad_q)
+        for (int d = 0; d < DIM; ++d) grad_q[i * DIM + d] = static_cast<T>(-(p * g / td) * tG[d]);
+    }
+  }
+}
+
+// FP64 dz contributions of the flagged queries, added in ascending query order.
+template <typename T, int DIM, int L, int PM>
+__global__ __launch_bounds__(kWG) void k_bwd_fixz(DevPts data, int64_t n, DevPts query, double p,
+                                                  unsigned flags, const int* __restrict__ list,
+                                                  const int* __restrict__ count,
+                                                  const double* __restrict__ slot_coef,
+                                                  const int* __restrict__ slot_hits,
+                                                  T* __restrict__ grad_z) {
+  const int cnt = *count;
+  if (cnt == 0) return;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (j >= n) return;
+  const bool excl = (flags & 1u) != 0;
+  const double nhp = -0.5 * p;
+  T c[3] = {T(0), T(0), T(0)}, v;
+  Loader<T, DIM, L>::data(data, j, c, v);
+  NSum acc;
+  for (int sl = 0; sl < cnt; ++sl) {
+    const int64_t i = list[sl];
+    if (excl && i == j) continue;
+    T qt[3] = {T(0), T(0), T(0)};
+    Loader<T, DIM, L>::query(query, i, qt);
+    double r2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double e = static_cast<double>(qt[d]) - static_cast<double>(c[d]);
+      r2 += e * e;
+    }
+    if (slot_hits[sl] > 0) {
+      if (r2 == 0.0) acc.add(slot_coef[sl]);
+    } else {
+      acc.add(slot_coef[sl] * weight<PM>(r2, nhp));
+    }
+  }
+  grad_z[j] = static_cast<T>(static_cast<double>(grad_z[j]) + acc.value());
+}
+
+// ---------------------------------------------------------------------------------------
+// Host launchers.
+// ---------------------------------------------------------------------------------------
+template <typename T, int DIM, int L, int PM>
+hipError_t launch_bwd_query_t(const BwdArgs& a, int split, int64_t chunk, double4* part,
+                              hipStream_t st) {
+  const bool ndp = (a.flags & 0x4u) != 0, ndq = (a.flags & 0x8u) != 0;
+  const int Q = a.q_per_lane;
+  const int64_t qpb = static_cast<int64_t>(kWG) * Q;
+  dim3 grid(static_cast<unsigned>((a.m + qpb - 1) / qpb), static_cast<unsigned>(split));
+  const T nhp = static_cast<T>(-0.5 * a.p);
+  const T* sz = static_cast<const T*>(a.saved_z);
+#define IDW_BQ(QQ, DP, DQ)                                                                  \
+  hipLaunchKernelGGL((k_bwd_query<T, DIM, L, PM, QQ, DP, DQ>), grid, dim3(kWG), 0, st,      \
+                     a.data, a.n, a.query, a.m, chunk, nhp, a.flags, a.hdr, sz, part)
+#define IDW_BQ_Q(QQ)                  \
+  case QQ:                            \
+    if (ndp && ndq)                   \
+      IDW_BQ(QQ, true, true);         \
+    else if (ndp)                     \
+      IDW_BQ(QQ, true, false);        \
+    else                              \
+      IDW_BQ(QQ, false, true);        \
+    break;
+  if constexpr (sizeof(T) == 4) {
+    switch (Q) {
+      IDW_BQ_Q(2)
+      IDW_BQ_Q(4)
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    switch (Q) {
+      IDW_BQ_Q(2)
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+#undef IDW_BQ_Q
+#undef IDW_BQ
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int L, int PM>
+hipError_t launch_bwd_data_t(const BwdArgs& a, int split, int64_t chunk, double* part,
+                             hipStream_t st) {
+  const int Q = a.q_per_lane;
+  const int64_t xpb = static_cast<int64_t>(kWG) * Q;
+  dim3 grid(static_cast<unsigned>((a.n + xpb - 1) / xpb), static_cast<unsigned>(split));
+  const T nhp = static_cast<T>(-0.5 * a.p);
+  const T* go = static_cast<const T*>(a.grad_out);
+#define IDW_BD_Q(QQ)                                                                        \
+  case QQ:                                                                                  \
+    hipLaunchKernelGGL((k_bwd_data<T, DIM, L, PM, QQ>), grid, dim3(kWG), 0, st, a.data,     \
+                       a.n, a.query, a.m, chunk, nhp, a.flags, a.hdr, go, a.saved_den, part); \
+    break;
+  if constexpr (sizeof(T) == 4) {
+    switch (Q) {
+      IDW_BD_Q(4)
+      IDW_BD_Q(8)
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    switch (Q) {
+      IDW_BD_Q(2)
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+#undef IDW_BD_Q
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int L, int PM>
+hipError_t launch_bwd_fix_t(const BwdArgs& a, hipStream_t st) {
+  const T* go = static_cast<const T*>(a.grad_out);
+  hipLaunchKernelGGL((k_bwd_fixq<T, DIM, L, PM>), dim3(a.fix_grid), dim3(kWG), 0, st, a.data,
+                     a.n, a.query, a.p, a.flags, a.list, a.count, go, static_cast<T*>(a.grad_q),
+                     a.slot_coef, a.slot_hits, a.slot_dp);
+  if (a.grad_z)
+    hipLaunchKernelGGL((k_bwd_fixz<T, DIM, L, PM>),
+                       dim3(static_cast<unsigned>((a.n + kWG - 1) / kWG)), dim3(kWG), 0, st,
+                       a.data, a.n, a.query, a.p, a.flags, a.list, a.count, a.slot_coef,
+                       a.slot_hits, static_cast<T*>(a.grad_z));
+  return hipGetLastError();
+}
+
+// Dispatch helpers over (precision, dim, weight class).
+// Backward weight classes: p = 2.5 runs on the general exp2/log2 form, which costs the
+// same two transcendentals once log2(r2) is needed for dp.
+#define IDW_DISPATCH_PM(FN, T, DIM, L, ...)                              \
+  switch (a.pmode) {                                                     \
+    case PM_1: return FN<T, DIM, L, PM_1>(__VA_ARGS__);                  \
+    case PM_2: return FN<T, DIM, L, PM_2>(__VA_ARGS__);                  \
+    case PM_3: return FN<T, DIM, L, PM_3>(__VA_ARGS__);                  \
+    case PM_4: return FN<T, DIM, L, PM_4>(__VA_ARGS__);                  \
+    default: return FN<T, DIM, L, PM_GEN>(__VA_ARGS__);                  \
+  }
+
+template <typename T, int DIM, int L>
+hipError_t bwd_query_pm(const BwdArgs& a, int split, int64_t chunk, double4* part, hipStream_t st) {
+  IDW_DISPATCH_PM(launch_bwd_query_t, T, DIM, L, a, split, chunk, part, st)
+}
+template <typename T, int DIM, int L>
+hipError_t bwd_data_pm(const BwdArgs& a, int split, int64_t chunk, double* part, hipStream_t st) {
+  IDW_DISPATCH_PM(launch_bwd_data_t, T, DIM, L, a, split, chunk, part, st)
+}
+template <typename T, int DIM, int L>
+hipError_t bwd_fix_pm(const BwdArgs& a, hipStream_t st) {
+  IDW_DISPATCH_PM(launch_bwd_fix_t, T, DIM, L, a, st)
+}
+
+template <typename T, int DIM>
+hipError_t launch_bwd_qmerge(const BwdArgs& a, int split, const double4* part, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((a.m + kWG - 1) / kWG));
+  hipLaunchKernelGGL((k_bwd_qmerge<T, DIM>), grid, dim3(kWG), 0, st, part, a.m, split, a.p, a.hdr,
+                     static_cast<const T*>(a.grad_out), a.saved_den, static_cast<T*>(a.grad_q),
+                     a.wg_dp);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bwd_zmerge(const BwdArgs& a, int split, const double* part, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((a.n + kWG - 1) / kWG));
+  hipLaunchKernelGGL((k_bwd_zmerge<T>), grid, dim3(kWG), 0, st, part, a.n, split,
+                     static_cast<T*>(a.grad_z));
+  return hipGetLastError();
+}
+
+}  // namespace idw

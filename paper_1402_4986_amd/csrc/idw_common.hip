@@ -1,0 +1,259 @@
+// Layout-independent kernels: extent/threshold header, split merge, deterministic
+// compaction of flagged queries, and the final dp reduction.
+#include <math.h>
+
+#include "idw_bwd.hpp"
+#include "idw_device.hpp"
+#include "idw_launch.hpp"
+
+namespace idw {
+
+// Reduces the per-workgroup bounding boxes and fills the workspace header.
+//  extent  = largest side of the data bounding box (1 if zero or not finite);
+//  s       = 2^-e with extent * s in [0.5, 1) for the FP32 sweep (keeps every weight of
+//            points inside the box far from FP32 overflow/underflow; exact scaling), 1 for FP64;
+//  flag thresholds: a query is recomputed in FP64 when its denominator exceeds
+//  (1e-6 * extent)^-p (some data point closer than 1e-6 of the extent, or an exact hit),
+//  or when it is not above the lower threshold (FP32 underflow of the weights).
+__global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ part, int nb,
+                                                    int dim, double p, int f32s,
+                                                    double* __restrict__ hdr) {
+  __shared__ double red[kWG];
+  const int t = threadIdx.x;
+  double ext = 0.0;
+  for (int d = 0; d < dim; ++d) {
+    double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
+    for (int b = t; b < nb; b += kWG) {
+      mn = fmin(mn, part[b * 6 + d]);
+      mx = fmax(mx, part[b * 6 + 3 + d]);
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      red[t] = pass ? mx : mn;
+      __syncthreads();
+      for (int s = kWG / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] = pass ? fmax(red[t], red[t + s]) : fmin(red[t], red[t + s]);
+        __syncthreads();
+      }
+      if (pass)
+        mx = red[0];
+      else
+        mn = red[0];
+      __syncthreads();
+    }
+    ext = fmax(ext, mx - mn);
+  }
+  if (t == 0) {
+    if (!(ext > 0.0) || !(ext < __builtin_huge_val())) ext = 1.0;
+    double s = 1.0;
+    if (f32s) {
+      int e = 0;
+      (void)frexp(ext, &e);
+      s = ldexp(1.0, -e);
+    }
+    const double unit = pow(s, p);
+    const double thr_s = pow(1e-6 * ext * s, -p);
+    const double lo_s = f32s ? ldexp(1.0, -60) : 0.0;
+    hdr[H_SCALE] = s;
+    hdr[H_THR_S] = thr_s;
+    hdr[H_LO_S] = lo_s;
+    hdr[H_DEN_UNIT] = unit;
+    hdr[H_THR_U] = thr_s * unit;
+    hdr[H_LO_U] = lo_s * unit;
+    hdr[H_EXTENT] = ext;
+  }
+}
+
+hipError_t bbox_final(const double* part, int nblocks, int dim, double p, bool f32_scaling,
+                      double* hdr, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kWG), 0, st, part, nblocks, dim, p,
+                     f32_scaling ? 1 : 0, hdr);
+  return hipGetLastError();
+}
+
+// Merges split partials in chunk order (TwoSum-compensated FP64) and finalises.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_merge(const double2* __restrict__ part, int64_t m,
+                                               int split, const double* __restrict__ hdr,
+                                               T* __restrict__ out_z, double* __restrict__ out_den,
+                                               uint8_t* __restrict__ flag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (i >= m) return;
+  double nh = 0.0, nl = 0.0, dh = 0.0, dl = 0.0;
+  for (int c = 0; c < split; ++c) {
+    const double2 v = part[static_cast<int64_t>(c) * m + i];
+    two_sum_acc(nh, nl, v.x);
+    two_sum_acc(dh, dl, v.y);
+  }
+  const double num = nh + nl, den = dh + dl;
+  const bool ok = den <= hdr[H_THR_S] && den > hdr[H_LO_S];
+  out_z[i] = static_cast<T>(num / den);
+  if (out_den) out_den[i] = den * hdr[H_DEN_UNIT];
+  flag[i] = ok ? 0 : 1;
+}
+
+hipError_t merge_split(const double2* part, int64_t m, int split, const double* hdr, void* out_z,
+                       bool f64, double* out_den, uint8_t* flag, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((m + kWG - 1) / kWG));
+  if (f64)
+    hipLaunchKernelGGL(k_merge<double>, grid, dim3(kWG), 0, st, part, m, split, hdr,
+                       static_cast<double*>(out_z), out_den, flag);
+  else
+    hipLaunchKernelGGL(k_merge<float>, grid, dim3(kWG), 0, st, part, m, split, hdr,
+                       static_cast<float*>(out_z), out_den, flag);
+  return hipGetLastError();
+}
+
+// Backward flag: the saved denominator (caller units) outside the FP32-safe range.
+__global__ __launch_bounds__(kWG) void k_flags_from_den(const double* __restrict__ den, int64_t m,
+                                                        const double* __restrict__ hdr,
+                                                        uint8_t* __restrict__ flag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (i >= m) return;
+  const double d = den[i];
+  flag[i] = (d <= hdr[H_THR_U] && d > hdr[H_LO_U]) ? 0 : 1;
+}
+
+hipError_t flags_from_den(const double* den, int64_t m, const double* hdr, uint8_t* flag,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_flags_from_den, dim3(static_cast<unsigned>((m + kWG - 1) / kWG)),
+                     dim3(kWG), 0, st, den, m, hdr, flag);
+  return hipGetLastError();
+}
+
+// ---- Deterministic, order-preserving compaction of flag bytes into an index list. ----
+// Block b owns flags [b*4096, (b+1)*4096); thread t owns 16 consecutive flags of it.
+constexpr int kPerThread = kCountBlock / kWG;
+
+__device__ __forceinline__ int local_count(const uint8_t* __restrict__ flag, int64_t m,
+                                           int64_t base) {
+  int c = 0;
+#pragma unroll
+  for (int u = 0; u < kPerThread; ++u) {
+    const int64_t i = base + u;
+    if (i < m) c += flag[i] ? 1 : 0;
+  }
+  return c;
+}
+
+__global__ __launch_bounds__(kWG) void k_count(const uint8_t* __restrict__ flag, int64_t m,
+                                               int* __restrict__ bcnt) {
+  __shared__ double red[kWG];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kCountBlock + threadIdx.x * kPerThread;
+  const double c = block_sum(static_cast<double>(local_count(flag, m, base)), red);
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = static_cast<int>(c);
+}
+
+// Exclusive scan of the block counts in place (single workgroup), total into *count.
+__global__ __launch_bounds__(kWG) void k_scan(int* __restrict__ bcnt, int nb,
+                                              int* __restrict__ count) {
+  __shared__ int buf[kWG];
+  __shared__ int carry;
+  const int t = threadIdx.x;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += kWG) {
+    const int v = (base + t < nb) ? bcnt[base + t] : 0;
+    buf[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kWG; off <<= 1) {  // Hillis-Steele inclusive scan
+      const int add = t >= off ? buf[t - off] : 0;
+      __syncthreads();
+      buf[t] += add;
+      __syncthreads();
+    }
+    if (base + t < nb) bcnt[base + t] = carry + buf[t] - v;
+    __syncthreads();
+    if (t == kWG - 1) carry += buf[t];
+    __syncthreads();
+  }
+  if (t == 0) *count = carry;
+}
+
+__global__ __launch_bounds__(kWG) void k_emit(const uint8_t* __restrict__ flag, int64_t m,
+                                              const int* __restrict__ boff,
+                                              int* __restrict__ list) {
+  __shared__ int buf[kWG];
+  const int t = threadIdx.x;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kCountBlock + t * kPerThread;
+  const int c = local_count(flag, m, base);
+  buf[t] = c;
+  __syncthreads();
+  for (int off = 1; off < kWG; off <<= 1) {
+    const int add = t >= off ? buf[t - off] : 0;
+    __syncthreads();
+    buf[t] += add;
+    __syncthreads();
+  }
+  int pos = boff[blockIdx.x] + buf[t] - c;
+  for (int u = 0; u < kPerThread; ++u) {
+    const int64_t i = base + u;
+    if (i < m && flag[i]) list[pos++] = static_cast<int>(i);
+  }
+}
+
+hipError_t compact_flags(const uint8_t* flag, int64_t m, int* bcnt, int* list, int* count,
+                         hipStream_t st) {
+  const int nb = static_cast<int>((m + kCountBlock - 1) / kCountBlock);
+  hipLaunchKernelGGL(k_count, dim3(nb), dim3(kWG), 0, st, flag, m, bcnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kWG), 0, st, bcnt, nb, count);
+  hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kWG), 0, st, flag, m, bcnt, list);
+  return hipGetLastError();
+}
+
+// dp = sum of the sweep workgroups' partials (in workgroup order) plus the FP64 fix-up
+// slots' partials (in ascending query order).  Single workgroup, fixed-order tree.
+__global__ __launch_bounds__(kWG) void k_dp_final(const double* __restrict__ wg_dp, int nwg,
+                                                  const double* __restrict__ slot_dp,
+                                                  const int* __restrict__ count,
+                                                  double* __restrict__ grad_p) {
+  __shared__ double red[kWG];
+  const int t = threadIdx.x;
+  double h = 0.0, l = 0.0;
+  for (int b = t; b < nwg; b += kWG) two_sum_acc(h, l, wg_dp[b]);
+  const int cnt = *count;
+  for (int b = t; b < cnt; b += kWG) two_sum_acc(h, l, slot_dp[b]);
+  const double tot = block_sum(h, red) + block_sum(l, red);
+  if (t == 0) *grad_p = tot;
+}
+
+hipError_t bwd_qmerge(const BwdArgs& a, bool f64, hipStream_t st) {
+  if (f64)
+    return a.dim == 3 ? launch_bwd_qmerge<double, 3>(a, a.split_q, a.part_q, st)
+                      : launch_bwd_qmerge<double, 2>(a, a.split_q, a.part_q, st);
+  return a.dim == 3 ? launch_bwd_qmerge<float, 3>(a, a.split_q, a.part_q, st)
+                    : launch_bwd_qmerge<float, 2>(a, a.split_q, a.part_q, st);
+}
+
+hipError_t bwd_zmerge(const BwdArgs& a, bool f64, hipStream_t st) {
+  if (f64) return launch_bwd_zmerge<double>(a, a.split_z, a.part_z, st);
+  return launch_bwd_zmerge<float>(a, a.split_z, a.part_z, st);
+}
+
+hipError_t dp_final(const double* wg_dp, int nwg, const double* slot_dp, const int* count,
+                    double* grad_p, hipStream_t st) {
+  hipLaunchKernelGGL(k_dp_final, dim3(1), dim3(kWG), 0, st, wg_dp, nwg, slot_dp, count, grad_p);
+  return hipGetLastError();
+}
+
+}  // namespace idw
+
+namespace idw {
+
+// Zero fill with a kernel (a memset node is never recorded into a captured graph).
+__global__ __launch_bounds__(kWG) void k_fill_zero(uint32_t* __restrict__ p, int64_t words) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; i < words;
+       i += static_cast<int64_t>(gridDim.x) * kWG)
+    p[i] = 0u;
+}
+
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const int64_t words = static_cast<int64_t>(bytes / 4);
+  if (words == 0) return hipSuccess;
+  int64_t blocks = (words + kWG - 1) / kWG;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_zero, dim3(static_cast<unsigned>(blocks)), dim3(kWG), 0, st,
+                     static_cast<uint32_t*>(p), words);
+  return hipGetLastError();
+}
+
+}  // namespace idw

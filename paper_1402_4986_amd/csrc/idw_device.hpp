@@ -1,0 +1,234 @@
+// Device-side building blocks shared by the IDW kernels (gfx950, wave64).
+//
+//  - record loaders for the five layouts of Sections 3.1-3.5 (SoA, AoS, aligned AoS,
+//    SoAoS, hybrid AoS + array of values), templated on element type and dimension;
+//  - the weight w = d^-p of Eq. 1 written through r^2 = d^2, with fast forms for
+//    p in {1, 2, 3, 4, 2.5} and the exp2/log2 form for any other p;
+//  - TwoSum accumulation into (hi, lo) pairs and fixed-order workgroup reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace idw {
+
+enum Layout { L_SOA = 0, L_AOS = 1, L_AOAS = 2, L_HYBRID = 3, L_SOAOS = 4 };
+
+// Weight forms, selected on the host from p.
+enum PMode { PM_GEN = 0, PM_1 = 1, PM_2 = 2, PM_3 = 3, PM_4 = 4, PM_25 = 5 };
+
+constexpr int kWG = 256;  // threads per workgroup of every sweep kernel (4 wave64)
+
+// Device-side view of a point set: the raw pointer slots of idw_points.
+struct DevPts {
+  const void* p[4];
+};
+
+// Four-wide record as staged in LDS: {x, y, z-or-value, value-or-pad}.
+template <typename T>
+struct alignas(4 * sizeof(T)) P4 {
+  T x, y, z, w;
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) P2 {
+  T x, y;
+};
+
+// ---------------------------------------------------------------------------------------
+// Record loaders.  c[0..DIM-1] receive coordinates, v the value (data points only).
+// ---------------------------------------------------------------------------------------
+template <typename T, int DIM, int L>
+struct Loader {
+  static __device__ __forceinline__ void data(const DevPts& P, int64_t j, T (&c)[3], T& v) {
+    if constexpr (L == L_SOA) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) c[k] = static_cast<const T*>(P.p[k])[j];
+      v = static_cast<const T*>(P.p[DIM])[j];
+    } else if constexpr (L == L_AOS) {
+      const T* r = static_cast<const T*>(P.p[0]) + j * (DIM + 1);
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) c[k] = r[k];
+      v = r[DIM];
+    } else if constexpr (L == L_AOAS) {
+      const P4<T> r = static_cast<const P4<T>*>(P.p[0])[j];
+      c[0] = r.x;
+      c[1] = r.y;
+      if constexpr (DIM == 3) {
+        c[2] = r.z;
+        v = r.w;
+      } else {
+        v = r.z;
+      }
+    } else if constexpr (L == L_HYBRID) {
+      const T* r = static_cast<const T*>(P.p[0]) + j * DIM;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) c[k] = r[k];
+      v = static_cast<const T*>(P.p[1])[j];
+    } else {  // L_SOAOS
+      if constexpr (DIM == 2) {
+        const P2<T> r = static_cast<const P2<T>*>(P.p[0])[j];
+        c[0] = r.x;
+        c[1] = r.y;
+      } else {
+        const P4<T> r = static_cast<const P4<T>*>(P.p[0])[j];
+        c[0] = r.x;
+        c[1] = r.y;
+        c[2] = r.z;
+      }
+      v = static_cast<const P2<T>*>(P.p[1])[j].x;
+    }
+  }
+
+  static __device__ __forceinline__ void query(const DevPts& P, int64_t i, T (&c)[3]) {
+    if constexpr (L == L_SOA) {
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) c[k] = static_cast<const T*>(P.p[k])[i];
+    } else if constexpr (L == L_AOS || L == L_HYBRID) {
+      const T* r = static_cast<const T*>(P.p[0]) + i * DIM;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) c[k] = r[k];
+    } else if constexpr (L == L_AOAS || (L == L_SOAOS && DIM == 3)) {
+      const P4<T> r = static_cast<const P4<T>*>(P.p[0])[i];
+      c[0] = r.x;
+      c[1] = r.y;
+      if constexpr (DIM == 3) c[2] = r.z;
+    } else {  // L_SOAOS, DIM == 2
+      const P2<T> r = static_cast<const P2<T>*>(P.p[0])[i];
+      c[0] = r.x;
+      c[1] = r.y;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+// Weight w = d^-p = (r2)^(-p/2) (Eq. 1).  nhp = -p/2 (used by the general form only).
+// FP32 uses the hardware transcendentals (about 1 ulp); FP64 uses correctly rounded
+// division and square root, and the double exp2/log2 for general p.
+// r2 == 0 gives +inf (flagged and recomputed); r2 == +inf (padding) gives 0.
+// ---------------------------------------------------------------------------------------
+template <int PM>
+__device__ __forceinline__ float weight(float r2, float nhp) {
+  if constexpr (PM == PM_2) {
+    return __builtin_amdgcn_rcpf(r2);
+  } else if constexpr (PM == PM_1) {
+    return __builtin_amdgcn_rsqf(r2);
+  } else if constexpr (PM == PM_3) {
+    const float s = __builtin_amdgcn_rsqf(r2);
+    return s * s * s;
+  } else if constexpr (PM == PM_4) {
+    const float t = __builtin_amdgcn_rcpf(r2);
+    return t * t;
+  } else if constexpr (PM == PM_25) {
+    const float s = __builtin_amdgcn_rsqf(r2);
+    return s * s * __builtin_amdgcn_sqrtf(s);
+  } else {
+    return __builtin_amdgcn_exp2f(nhp * __builtin_amdgcn_logf(r2));
+  }
+}
+
+template <int PM>
+__device__ __forceinline__ double weight(double r2, double nhp) {
+  if constexpr (PM == PM_2) {
+    return 1.0 / r2;
+  } else if constexpr (PM == PM_1) {
+    return 1.0 / sqrt(r2);
+  } else if constexpr (PM == PM_3) {
+    const double s = 1.0 / sqrt(r2);
+    return s * s * s;
+  } else if constexpr (PM == PM_4) {
+    const double t = 1.0 / r2;
+    return t * t;
+  } else if constexpr (PM == PM_25) {
+    const double s = 1.0 / sqrt(r2);
+    return s * s * sqrt(s);
+  } else {
+    return exp2(nhp * log2(r2));
+  }
+}
+
+// w / r2 given w (for the query-position gradient), in the same arithmetic.
+template <int PM>
+__device__ __forceinline__ float weight_over_r2(float w, float r2) {
+  if constexpr (PM == PM_2) {
+    return w * w;  // w = 1/r2
+  } else if constexpr (PM == PM_4) {
+    return w * __builtin_amdgcn_sqrtf(w);  // w = r2^-2 -> r2^-3 = w^1.5
+  } else {
+    return w * __builtin_amdgcn_rcpf(r2);
+  }
+}
+
+template <int PM>
+__device__ __forceinline__ double weight_over_r2(double w, double r2) {
+  return w / r2;
+}
+
+// ---------------------------------------------------------------------------------------
+// Compensated accumulation: (hi, lo) += x with Knuth's TwoSum (no magnitude assumption).
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void two_sum_acc(T& hi, T& lo, T x) {
+  const T s = hi + x;
+  const T bb = s - hi;
+  const T e = (hi - (s - bb)) + (x - bb);
+  hi = s;
+  lo += e;
+}
+
+// Neumaier accumulator for the FP64 fix-up paths.
+struct NSum {
+  double s = 0.0, c = 0.0;
+  __device__ __forceinline__ void add(double v) {
+    const double t = s + v;
+    if (fabs(s) >= fabs(v))
+      c += (s - t) + v;
+    else
+      c += (v - t) + s;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return s + c; }
+};
+
+// Fixed-order tree sum over the kWG threads of a workgroup.  `red` is LDS scratch of
+// kWG doubles; every thread receives the total.  Contains barriers: call uniformly.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kWG / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ long long block_sum_i64(long long v, long long* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kWG / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const long long r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Workspace header (doubles), written by the extent kernel of every call.
+enum HdrSlot {
+  H_SCALE = 0,     // power of two s applied to coordinates in the FP32 sweep (1 for FP64)
+  H_THR_S = 1,     // upper flag threshold on the denominator, scaled units
+  H_LO_S = 2,      // lower flag threshold on the denominator, scaled units
+  H_DEN_UNIT = 3,  // factor s^p converting a scaled denominator to caller units
+  H_THR_U = 4,     // upper flag threshold, caller units
+  H_LO_U = 5,      // lower flag threshold, caller units
+  H_EXTENT = 6,    // data extent (largest side of the bounding box; 1 if degenerate)
+  H_COUNT_I = 32   // int slots start at byte 256: [0] flagged count
+};
+
+}  // namespace idw

@@ -1,0 +1,367 @@
+// Forward sweep of Shepard IDW (Section 2.1, Eq. 1) for gfx950.
+//
+// One workgroup = 256 lanes x Q queries held in registers.  Data points are streamed
+// through LDS in tiles of kTile records (double-buffered: the global loads of tile t+1 are
+// in flight while tile t is consumed), and every record is broadcast from LDS to all lanes
+// of the wavefront (the shared-memory tiling of Section 4.2, re-derived for wave64).  Each
+// lane accumulates sum w*z and sum w for its queries in plain arithmetic over 64-record
+// blocks and folds every block into (hi, lo) pairs with TwoSum, so the sum error is that of
+// a 64-term sum, not of an n-term one.  The ratio is taken in FP64.  A query whose
+// denominator exceeds the near-coincidence threshold (or is not finite) is flagged for the
+// FP64 fix-up kernel, which recomputes it exactly, including the exact-hit rule.
+#pragma once
+
+#include <math.h>
+
+#include "idw_device.hpp"
+#include "idw_launch.hpp"
+
+namespace idw {
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ T infT() {
+  return __builtin_huge_valf();
+}
+template <>
+__device__ __forceinline__ double infT<double>() {
+  return __builtin_huge_val();
+}
+
+// Squared distance from query coordinates q to a staged record d.
+template <typename T, int DIM>
+__device__ __forceinline__ T sqdist(const T (&q)[3], const P4<T>& d) {
+  const T dx = q[0] - d.x;
+  const T dy = q[1] - d.y;
+  T r2 = dx * dx;
+  r2 = fmaT(dy, dy, r2);
+  if constexpr (DIM == 3) {
+    const T dz = q[2] - d.z;
+    r2 = fmaT(dz, dz, r2);
+  }
+  return r2;
+}
+
+// Stage one record into LDS form: coordinates scaled by s; {x, y, v, 0} or {x, y, z, v}.
+template <typename T, int DIM>
+__device__ __forceinline__ P4<T> stage(const T (&c)[3], T v, T s) {
+  P4<T> r;
+  r.x = c[0] * s;
+  r.y = c[1] * s;
+  if constexpr (DIM == 3) {
+    r.z = c[2] * s;
+    r.w = v;
+  } else {
+    r.z = v;
+    r.w = T(0);
+  }
+  return r;
+}
+
+// Consume one LDS tile: for each of the lane's Q queries, accumulate w*z and w.
+template <typename T, int DIM, int PM, int Q, bool DIAG>
+__device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t jt,
+                                         const T (&qc)[Q][3], const int64_t (&qi)[Q], T nhp,
+                                         T (&nh)[Q], T (&nl)[Q], T (&dh)[Q], T (&dl)[Q]) {
+  constexpr int CH = 64;
+  for (int c0 = 0; c0 < kTile; c0 += CH) {
+    T an[Q], ad[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      an[k] = T(0);
+      ad[k] = T(0);
+    }
+#pragma unroll 4
+    for (int jj = 0; jj < CH; ++jj) {
+      const P4<T> d = tl[c0 + jj];
+      const T dv = (DIM == 3) ? d.w : d.z;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const T r2 = sqdist<T, DIM>(qc[k], d);
+        T w = weight<PM>(r2, nhp);
+        if constexpr (DIAG) {
+          if (jt + c0 + jj == qi[k]) w = T(0);
+        }
+        an[k] = fmaT(w, dv, an[k]);
+        ad[k] += w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      two_sum_acc(nh[k], nl[k], an[k]);
+      two_sum_acc(dh[k], dl[k], ad[k]);
+    }
+  }
+}
+
+// Finalise one query from its (num, den) in scaled units.
+template <typename T>
+__device__ __forceinline__ void fwd_finish(int64_t i, double num, double den, const double* hdr,
+                                           T* __restrict__ out_z, double* __restrict__ out_den,
+                                           uint8_t* __restrict__ out_flag) {
+  const bool ok = den <= hdr[H_THR_S] && den > hdr[H_LO_S];
+  out_z[i] = static_cast<T>(num / den);
+  if (out_den) out_den[i] = den * hdr[H_DEN_UNIT];
+  out_flag[i] = ok ? 0 : 1;
+}
+
+template <typename T, int DIM, int L, int PM, int Q>
+__global__ __launch_bounds__(kWG) void k_fwd_sweep(DevPts data, int64_t n, DevPts query, int64_t m,
+                                                   int64_t chunk, int split, T nhp, unsigned flags,
+                                                   const double* __restrict__ hdr,
+                                                   T* __restrict__ out_z,
+                                                   double* __restrict__ out_den,
+                                                   uint8_t* __restrict__ out_flag,
+                                                   double2* __restrict__ part) {
+  __shared__ P4<T> tile[2][kTile];
+  const int tid = threadIdx.x;
+  const int64_t q0 = static_cast<int64_t>(blockIdx.x) * (kWG * Q);
+  const int64_t jb = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t je = (jb + chunk < n) ? jb + chunk : n;
+  const T s = static_cast<T>(hdr[H_SCALE]);
+
+  T qc[Q][3];
+  int64_t qi[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    qi[k] = q0 + tid + static_cast<int64_t>(k) * kWG;
+    T c[3] = {T(0), T(0), T(0)};
+    if (qi[k] < m) Loader<T, DIM, L>::query(query, qi[k], c);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) qc[k][d] = c[d] * s;
+  }
+  T nh[Q], nl[Q], dh[Q], dl[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) nh[k] = nl[k] = dh[k] = dl[k] = T(0);
+
+  T rc[2][3], rv[2];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t j = jb + static_cast<int64_t>(t) * kTile + u * kWG + tid;
+      if (j < je) {
+        Loader<T, DIM, L>::data(data, j, rc[u], rv[u]);
+      } else {  // padding record: infinitely far, zero value -> weight 0
+        rc[u][0] = rc[u][1] = rc[u][2] = infT<T>();
+        rv[u] = T(0);
+      }
+    }
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) tile[b][u * kWG + tid] = stage<T, DIM>(rc[u], rv[u], s);
+  };
+
+  const int ntiles = static_cast<int>((je - jb + kTile - 1) / kTile);
+  const bool excl = (flags & 1u) != 0;
+  fetch(0);
+  put(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) fetch(t + 1);
+    const int64_t jt = jb + static_cast<int64_t>(t) * kTile;
+    const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
+    if (diag)
+      fwd_tile<T, DIM, PM, Q, true>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
+    else
+      fwd_tile<T, DIM, PM, Q, false>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
+    if (t + 1 < ntiles) put((t + 1) & 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (qi[k] < m) {
+      const double num = static_cast<double>(nh[k]) + static_cast<double>(nl[k]);
+      const double den = static_cast<double>(dh[k]) + static_cast<double>(dl[k]);
+      if (split == 1)
+        fwd_finish<T>(qi[k], num, den, hdr, out_z, out_den, out_flag);
+      else
+        part[static_cast<int64_t>(blockIdx.y) * m + qi[k]] = make_double2(num, den);
+    }
+  }
+}
+
+// FP64 recomputation of flagged queries: one workgroup per query, data strided over the
+// workgroup's lanes (ceil(n / 256) records per lane), exact d == 0 detection, Neumaier
+// sums per lane and a fixed-order tree reduction.  Writes Z and D (caller units; +inf
+// for an exact hit, whose Z is the mean of the coincident values).
+template <typename T, int DIM, int L, int PM>
+__global__ __launch_bounds__(kWG) void k_fwd_fixup(DevPts data, int64_t n, DevPts query,
+                                                   double nhp, unsigned flags,
+                                                   const int* __restrict__ list,
+                                                   const int* __restrict__ count,
+                                                   T* __restrict__ out_z,
+                                                   double* __restrict__ out_den) {
+  __shared__ double red[kWG];
+  __shared__ long long redi[kWG];
+  const int cnt = *count;
+  const bool excl = (flags & 1u) != 0;
+  for (int sl = blockIdx.x; sl < cnt; sl += gridDim.x) {
+    const int64_t i = list[sl];
+    T qt[3] = {T(0), T(0), T(0)};
+    Loader<T, DIM, L>::query(query, i, qt);
+    NSum num, den;
+    double hz = 0.0;
+    long long h = 0;
+    for (int64_t j = threadIdx.x; j < n; j += kWG) {
+      if (excl && j == i) continue;
+      T c[3] = {T(0), T(0), T(0)}, v;
+      Loader<T, DIM, L>::data(data, j, c, v);
+      double r2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double e = static_cast<double>(qt[d]) - static_cast<double>(c[d]);
+        r2 += e * e;
+      }
+      if (r2 == 0.0) {
+        ++h;
+        hz += static_cast<double>(v);
+      } else {
+        const double w = weight<PM>(r2, nhp);
+        num.add(w * static_cast<double>(v));
+        den.add(w);
+      }
+    }
+    const double tn = block_sum(num.value(), red);
+    const double td = block_sum(den.value(), red);
+    const double thz = block_sum(hz, red);
+    const long long th = block_sum_i64(h, redi);
+    if (threadIdx.x == 0) {
+      const double Z = th > 0 ? thz / static_cast<double>(th) : tn / td;
+      out_z[i] = static_cast<T>(Z);
+      if (out_den) out_den[i] = th > 0 ? __builtin_huge_val() : td;
+    }
+  }
+}
+
+// Per-workgroup bounding box of the data coordinates: part[b*6 + d] = min, [+3] = max.
+template <typename T, int DIM, int L>
+__global__ __launch_bounds__(kWG) void k_bbox(DevPts data, int64_t n, double* __restrict__ part) {
+  __shared__ double red[kWG];
+  double mn[3] = {__builtin_huge_val(), __builtin_huge_val(), __builtin_huge_val()};
+  double mx[3] = {-__builtin_huge_val(), -__builtin_huge_val(), -__builtin_huge_val()};
+  for (int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; j < n;
+       j += static_cast<int64_t>(gridDim.x) * kWG) {
+    T c[3] = {T(0), T(0), T(0)}, v;
+    Loader<T, DIM, L>::data(data, j, c, v);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      mn[d] = fmin(mn[d], static_cast<double>(c[d]));
+      mx[d] = fmax(mx[d], static_cast<double>(c[d]));
+    }
+  }
+  const int t = threadIdx.x;
+  for (int d = 0; d < DIM; ++d) {
+    for (int pass = 0; pass < 2; ++pass) {
+      red[t] = pass ? mx[d] : mn[d];
+      __syncthreads();
+      for (int s = kWG / 2; s > 0; s >>= 1) {
+        if (t < s) red[t] = pass ? fmax(red[t], red[t + s]) : fmin(red[t], red[t + s]);
+        __syncthreads();
+      }
+      if (t == 0) part[blockIdx.x * 6 + pass * 3 + d] = red[0];
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host launchers for one layout (instantiated once per layout translation unit).
+// ---------------------------------------------------------------------------------------
+template <typename T, int DIM, int L, int PM>
+hipError_t launch_fwd_sweep_q(const FwdArgs& a, hipStream_t st) {
+  const int Q = a.q_per_lane;
+  const int64_t qpb = static_cast<int64_t>(kWG) * Q;
+  dim3 grid(static_cast<unsigned>((a.m + qpb - 1) / qpb), static_cast<unsigned>(a.split));
+  const T nhp = static_cast<T>(-0.5 * a.p);
+  T* z = static_cast<T*>(a.out_z);
+#define IDW_FWD_Q(QQ)                                                                       \
+  case QQ:                                                                                  \
+    hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, QQ>), grid, dim3(kWG), 0, st, a.data,   \
+                       a.n, a.query, a.m, a.chunk, a.split, nhp, a.flags, a.hdr, z,         \
+                       a.out_den, a.flag, a.part);                                          \
+    break;
+  if constexpr (sizeof(T) == 4) {
+    switch (Q) {
+      IDW_FWD_Q(4)
+      IDW_FWD_Q(8)
+      default:
+        return hipErrorInvalidValue;
+    }
+  } else {
+    switch (Q) {
+      IDW_FWD_Q(2)
+      IDW_FWD_Q(4)
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+#undef IDW_FWD_Q
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int L>
+hipError_t launch_fwd_sweep_pm(const FwdArgs& a, hipStream_t st) {
+  switch (a.pmode) {
+    case PM_1: return launch_fwd_sweep_q<T, DIM, L, PM_1>(a, st);
+    case PM_2: return launch_fwd_sweep_q<T, DIM, L, PM_2>(a, st);
+    case PM_3: return launch_fwd_sweep_q<T, DIM, L, PM_3>(a, st);
+    case PM_4: return launch_fwd_sweep_q<T, DIM, L, PM_4>(a, st);
+    case PM_25: return launch_fwd_sweep_q<T, DIM, L, PM_25>(a, st);
+    default: return launch_fwd_sweep_q<T, DIM, L, PM_GEN>(a, st);
+  }
+}
+
+template <int L>
+hipError_t launch_fwd_sweep(const FwdArgs& a, bool f64, hipStream_t st) {
+  if (f64) return a.dim == 3 ? launch_fwd_sweep_pm<double, 3, L>(a, st) : launch_fwd_sweep_pm<double, 2, L>(a, st);
+  return a.dim == 3 ? launch_fwd_sweep_pm<float, 3, L>(a, st) : launch_fwd_sweep_pm<float, 2, L>(a, st);
+}
+
+template <typename T, int DIM, int L, int PM>
+hipError_t launch_fwd_fixup_t(const FwdArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_fwd_fixup<T, DIM, L, PM>), dim3(a.fix_grid), dim3(kWG), 0, st, a.data,
+                     a.n, a.query, -0.5 * a.p, a.flags, a.list, a.count,
+                     static_cast<T*>(a.out_z), a.out_den);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int L>
+hipError_t launch_fwd_fixup_pm(const FwdArgs& a, hipStream_t st) {
+  switch (a.pmode) {
+    case PM_1: return launch_fwd_fixup_t<T, DIM, L, PM_1>(a, st);
+    case PM_2: return launch_fwd_fixup_t<T, DIM, L, PM_2>(a, st);
+    case PM_3: return launch_fwd_fixup_t<T, DIM, L, PM_3>(a, st);
+    case PM_4: return launch_fwd_fixup_t<T, DIM, L, PM_4>(a, st);
+    case PM_25: return launch_fwd_fixup_t<T, DIM, L, PM_25>(a, st);
+    default: return launch_fwd_fixup_t<T, DIM, L, PM_GEN>(a, st);
+  }
+}
+
+template <int L>
+hipError_t launch_fwd_fixup(const FwdArgs& a, bool f64, hipStream_t st) {
+  if (f64) return a.dim == 3 ? launch_fwd_fixup_pm<double, 3, L>(a, st) : launch_fwd_fixup_pm<double, 2, L>(a, st);
+  return a.dim == 3 ? launch_fwd_fixup_pm<float, 3, L>(a, st) : launch_fwd_fixup_pm<float, 2, L>(a, st);
+}
+
+template <int L>
+hipError_t launch_bbox(const DevPts& d, int64_t n, int dim, bool f64, double* part, int nb,
+                       hipStream_t st) {
+  if (f64) {
+    if (dim == 3)
+      hipLaunchKernelGGL((k_bbox<double, 3, L>), dim3(nb), dim3(kWG), 0, st, d, n, part);
+    else
+      hipLaunchKernelGGL((k_bbox<double, 2, L>), dim3(nb), dim3(kWG), 0, st, d, n, part);
+  } else {
+    if (dim == 3)
+      hipLaunchKernelGGL((k_bbox<float, 3, L>), dim3(nb), dim3(kWG), 0, st, d, n, part);
+    else
+      hipLaunchKernelGGL((k_bbox<float, 2, L>), dim3(nb), dim3(kWG), 0, st, d, n, part);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace idw

@@ -1,0 +1,100 @@
+// Host-side launch descriptors shared by the C-ABI layer and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "idw_device.hpp"
+
+namespace idw {
+
+// Everything a forward launch needs; pointers are device pointers.
+struct FwdArgs {
+  DevPts data;
+  int64_t n = 0;
+  DevPts query;
+  int64_t m = 0;
+  int dim = 2;
+  int pmode = PM_GEN;
+  double p = 2.0;
+  unsigned flags = 0;
+  int q_per_lane = 8;
+  int split = 1;
+  int64_t chunk = 0;  // data points per split chunk (multiple of the tile)
+  const double* hdr = nullptr;
+  void* out_z = nullptr;
+  double* out_den = nullptr;
+  uint8_t* flag = nullptr;
+  double2* part = nullptr;
+  const int* list = nullptr;
+  const int* count = nullptr;
+  int fix_grid = 256;
+};
+
+// Everything a backward launch needs.
+struct BwdArgs {
+  DevPts data;
+  int64_t n = 0;
+  DevPts query;
+  int64_t m = 0;
+  int dim = 2;
+  int pmode = PM_GEN;
+  double p = 2.0;
+  unsigned flags = 0;
+  int q_per_lane = 4;    // query sweep: queries per lane
+  int x_per_lane = 4;    // data sweep: data points per lane
+  int split_q = 1;       // data chunks of the query sweep
+  int64_t chunk_q = 0;
+  int split_z = 1;       // query chunks of the data sweep
+  int64_t chunk_z = 0;
+  double4* part_q = nullptr;  // [split_q][m] (P, Gx, Gy, Gz)
+  double* part_z = nullptr;   // [split_z][n]
+  const double* hdr = nullptr;
+  const void* grad_out = nullptr;
+  const void* saved_z = nullptr;
+  const double* saved_den = nullptr;
+  void* grad_z = nullptr;
+  void* grad_q = nullptr;
+  double* wg_dp = nullptr;      // [num query workgroups] dp partials of the FP32/FP64 sweep
+  const int* list = nullptr;    // flagged queries, ascending
+  const int* count = nullptr;
+  double* slot_coef = nullptr;  // [m] per flagged slot: g/D (or g/h at a hit)
+  int* slot_hits = nullptr;     // [m] per flagged slot: hit count h
+  double* slot_dp = nullptr;    // [m] per flagged slot: dp contribution
+  int fix_grid = 256;
+};
+
+constexpr int kTile = 512;        // data points staged in LDS per tile (2 per thread)
+constexpr int kCountBlock = 4096; // flags per compaction block (16 per thread)
+
+// Per-layout entry points (one translation unit per layout keeps builds parallel).
+#define IDW_DECLARE_LAYOUT(NAME)                                                 \
+  hipError_t fwd_sweep_##NAME(const FwdArgs& a, bool f64, hipStream_t st);       \
+  hipError_t fwd_fixup_##NAME(const FwdArgs& a, bool f64, hipStream_t st);       \
+  hipError_t bbox_##NAME(const DevPts& d, int64_t n, int dim, bool f64, double* part, \
+                         int nblocks, hipStream_t st);                           \
+  hipError_t bwd_query_##NAME(const BwdArgs& a, bool f64, hipStream_t st);       \
+  hipError_t bwd_data_##NAME(const BwdArgs& a, bool f64, hipStream_t st);        \
+  hipError_t bwd_fixup_##NAME(const BwdArgs& a, bool f64, hipStream_t st);
+
+IDW_DECLARE_LAYOUT(soa)
+IDW_DECLARE_LAYOUT(aos)
+IDW_DECLARE_LAYOUT(aoas)
+IDW_DECLARE_LAYOUT(hybrid)
+IDW_DECLARE_LAYOUT(soaos)
+
+// Layout-independent kernels (idw_common.hip).
+hipError_t bbox_final(const double* part, int nblocks, int dim, double p, bool f32_scaling,
+                      double* hdr, hipStream_t st);
+hipError_t merge_split(const double2* part, int64_t m, int split, const double* hdr,
+                       void* out_z, bool f64, double* out_den, uint8_t* flag, hipStream_t st);
+hipError_t compact_flags(const uint8_t* flag, int64_t m, int* bcnt, int* list, int* count,
+                         hipStream_t st);
+hipError_t flags_from_den(const double* den, int64_t m, const double* hdr, uint8_t* flag,
+                          hipStream_t st);
+hipError_t bwd_qmerge(const BwdArgs& a, bool f64, hipStream_t st);
+hipError_t bwd_zmerge(const BwdArgs& a, bool f64, hipStream_t st);
+hipError_t dp_final(const double* wg_dp, int nwg, const double* slot_dp, const int* count,
+                    double* grad_p, hipStream_t st);
+
+}  // namespace idw

@@ -1,0 +1,148 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+function include/idw.h declares, reports record sizes that match the layout arithmetic
+printed in Sections 3.2-3.3, and rejects bad arguments before touching the device."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_1402_4986_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libidw.so not built")
+    return _lib.load()
+
+
+def test_every_declared_function_is_exported(lib):
+    hdr = open(os.path.join(ROOT, "include", "idw.h")).read()
+    declared = set(re.findall(r"\b(idw_[a-z_]+)\s*\(", hdr))
+    assert declared == set(_lib.EXPORTED)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.idw_version().decode().startswith("idw-gfx950")
+
+
+def _rb(lib, layout, dim, prec, is_data):
+    b = (ctypes.c_size_t * 4)()
+    rc = lib.idw_record_bytes(layout, dim, prec, is_data, b)
+    return rc, list(b)
+
+
+def test_record_sizes_follow_the_papers_layout_arithmetic(lib):
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_layout_arith.json")))
+    # AoS: three 32-bit members, no padding (x, y, value for 2-D data).
+    rc, b = _rb(lib, _lib.AOS, 2, _lib.FP32, 1)
+    assert rc == 0 and b[0] * 8 == g["aos_record_members"] * g["member_bits_f32"]
+    # AoaS FP32: aligned to 128 bits, hidden pad 128 - 3*32 = 32 bits.
+    rc, b = _rb(lib, _lib.AOAS, 2, _lib.FP32, 1)
+    assert rc == 0 and b[0] * 8 == g["aoas_alignment_bits"]
+    assert b[0] * 8 - g["aos_record_members"] * g["member_bits_f32"] == g["aoas_f32_hidden_pad_bits"]
+    # AoaS FP64: 64*3 + 64 = 2*128 bits.
+    rc, b = _rb(lib, _lib.AOAS, 2, _lib.FP64, 1)
+    assert rc == 0 and b[0] * 8 == g["aoas_f64_record_bits"]
+    assert b[0] * 8 == 3 * 64 + g["aoas_f64_hidden_pad_bits"] == g["aoas_f64_accesses_of_128_bits"] * 128
+
+
+def test_record_sizes_all_layouts(lib):
+    assert _rb(lib, _lib.SOA, 3, _lib.FP32, 1) == (0, [4, 4, 4, 4])
+    assert _rb(lib, _lib.SOA, 2, _lib.FP64, 0) == (0, [8, 8, 0, 0])
+    assert _rb(lib, _lib.AOS, 3, _lib.FP32, 0) == (0, [12, 0, 0, 0])
+    assert _rb(lib, _lib.AOAS, 3, _lib.FP32, 0) == (0, [16, 0, 0, 0])
+    assert _rb(lib, _lib.HYBRID, 2, _lib.FP64, 1) == (0, [16, 8, 0, 0])
+    assert _rb(lib, _lib.SOAOS, 2, _lib.FP64, 1) == (0, [16, 16, 0, 0])
+    assert _rb(lib, _lib.SOAOS, 3, _lib.FP32, 1) == (0, [16, 8, 0, 0])
+    assert _rb(lib, 9, 2, _lib.FP32, 1)[0] == _lib.IDW_EINVAL
+    assert _rb(lib, _lib.SOA, 4, _lib.FP32, 1)[0] == _lib.IDW_EINVAL
+
+
+def _pts(n, dim, layout, base=0x10000, stride=0x100000):
+    s = _lib.IdwPoints()
+    for k in range(4):
+        s.ptr[k] = base + k * stride
+    s.n, s.dim, s.layout = n, dim, layout
+    return s
+
+
+def _fwd(lib, data, query, p=2.0, prec=_lib.FP32, flags=0, ws=0x4000000, wsb=1 << 30, out=0x8000000):
+    return lib.idw_forward(ctypes.byref(data), ctypes.byref(query), p, prec, flags, out, None, ws, wsb, None, None)
+
+
+@pytest.mark.parametrize("case,code", [
+    ("dim", _lib.IDW_EINVAL), ("p0", _lib.IDW_EINVAL), ("pnan", _lib.IDW_EINVAL), ("pbig", _lib.IDW_EINVAL),
+    ("nulldata", _lib.IDW_EINVAL), ("n0", _lib.IDW_EINVAL), ("misaligned", _lib.IDW_EINVAL),
+    ("layoutmix", _lib.IDW_EUNSUPPORTED), ("excl", _lib.IDW_EINVAL), ("prec", _lib.IDW_EINVAL),
+    ("flags", _lib.IDW_EINVAL), ("ws", _lib.IDW_EWORKSPACE), ("wsalign", _lib.IDW_EWORKSPACE),
+])
+def test_bad_arguments_are_rejected_on_the_host(lib, case, code):
+    d = _pts(1000, 2, _lib.AOAS)
+    q = _pts(500, 2, _lib.AOAS, base=0x20000000)
+    kw = {}
+    if case == "dim":
+        d.dim = q.dim = 4
+    elif case == "p0":
+        kw["p"] = 0.0
+    elif case == "pnan":
+        kw["p"] = float("nan")
+    elif case == "pbig":
+        kw["p"] = 65.0
+    elif case == "nulldata":
+        d.ptr[0] = None
+    elif case == "n0":
+        d.n = 0
+    elif case == "misaligned":
+        d.ptr[0] = 0x10008
+    elif case == "layoutmix":
+        q.layout = _lib.SOA
+    elif case == "excl":
+        kw["flags"] = _lib.EXCLUDE_SELF
+    elif case == "prec":
+        kw["prec"] = 7
+    elif case == "flags":
+        kw["flags"] = 0x40
+    elif case == "ws":
+        kw["wsb"] = 16
+    elif case == "wsalign":
+        kw["ws"] = 0x4000010
+    rc = _fwd(lib, d, q, **kw)
+    assert rc == code, lib.idw_last_error().decode()
+    assert lib.idw_last_error().decode() != ""
+
+
+def test_zero_queries_is_a_no_op(lib):
+    d = _pts(1000, 3, _lib.SOA)
+    q = _pts(0, 3, _lib.SOA)
+    assert _fwd(lib, d, q, out=0) == 0
+
+
+def test_workspace_size_grows_with_queries(lib):
+    d = _pts(4096, 2, _lib.SOA)
+    sizes = []
+    for m in (1, 1000, 100000):
+        q = _pts(m, 2, _lib.SOA)
+        b = ctypes.c_size_t()
+        assert lib.idw_workspace_size(ctypes.byref(d), ctypes.byref(q), _lib.FP32, None, ctypes.byref(b)) == 0
+        sizes.append(b.value)
+    assert sizes[0] < sizes[1] < sizes[2]
+
+
+def test_backward_argument_checks(lib):
+    d = _pts(1000, 2, _lib.HYBRID)
+    q = _pts(10, 2, _lib.HYBRID, base=0x20000000)
+    args = [ctypes.byref(d), ctypes.byref(q), 2.0, _lib.FP32]
+    rc = lib.idw_backward(*args, 0, 1, 1, 1, None, None, None, 0x4000000, 1 << 30, None, None)
+    assert rc == _lib.IDW_EINVAL  # no gradient requested
+    rc = lib.idw_backward(*args, _lib.NEED_DZ, 1, 1, 1, None, None, None, 0x4000000, 1 << 30, None, None)
+    assert rc == _lib.IDW_EINVAL  # grad_z missing
+
+
+def test_batched_is_declared(lib):
+    plan = ctypes.c_void_p()
+    rc = lib.idw_batched_plan_create(None, 0, _lib.FP32, None, ctypes.byref(plan))
+    assert rc != 0

@@ -1,0 +1,163 @@
+"""GPU forward parity against the FP64 oracle (element by element), through the C ABI.
+
+Tolerances (stated by the workload definition): FP32 path 1e-5 and FP64 path 1e-12,
+relative to the summation scale S_i = sum_j w_ij |z_j| / sum_j w_ij (>= |Z_i|), so that
+queries where Z crosses zero are measured against the conditioning of their sum.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import TOL, gpu_forward, points, rand_case, scaled_err
+from paper_1402_4986_amd import api, workloads
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = ["soa", "aos", "aoas", "hybrid", "soaos"]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("p", [1.0, 2.0, 2.5, 3.0, 4.0, 1.7])
+def test_forward_matches_oracle_small(layout, prec, dim, p):
+    # 3000 data points = 5 full LDS tiles + a ragged one; 1337 queries = ragged query block.
+    x, z, q = rand_case(100 + dim, 3000, 1337, dim, prec)
+    print(f"case layout={layout} prec={prec} dim={dim} p={p}", flush=True)
+    Z, D = gpu_forward(x, z, q, p, layout, prec)
+    ref = oracle.forward(x, z, q, p)
+    err = scaled_err(Z, ref)
+    assert np.max(err) <= TOL[prec], f"max scaled err {np.max(err):.3e}"
+    np.testing.assert_allclose(D, ref["D"], rtol=10 * TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_exact_hits_duplicates_and_near_coincident_points(prec):
+    x, z, q = rand_case(7, 2000, 600, 2, prec)
+    x[11] = x[10]                       # duplicate location with a different value
+    q[:50] = x[:50]                     # exact hits (q[10], q[11] hit the duplicate pair)
+    q[50:60] = x[100:110] + 3e-7        # closer than 1e-6 of the extent: FP64 path
+    t = np.float32 if prec == "f32" else np.float64
+    q = q.astype(t).astype(np.float64)
+    Z, D = gpu_forward(x, z, q, 2.0, "aoas", prec)
+    ref = oracle.forward(x, z, q, 2.0)
+    hits = ref["H"] > 0
+    assert hits[:50].all()
+    # exact hit: the data value (mean of duplicates), rounded once to the output type
+    np.testing.assert_array_equal(Z[hits], ref["Z"][hits].astype(t).astype(np.float64))
+    assert np.all(np.isinf(D[hits]))
+    # near-coincident queries are recomputed in FP64: only the output rounding remains
+    assert not hits[50:60].any()
+    near = scaled_err(Z[50:60], {"Z": ref["Z"][50:60], "S": ref["S"][50:60]})
+    assert np.max(near) <= (6e-8 if prec == "f32" else 1e-14)
+    assert np.max(scaled_err(Z, ref)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("p", [2.0, 2.5])
+def test_leave_one_out_matches_oracle(prec, p):
+    x, z, _ = rand_case(8, 2500, 1, 2, prec)
+    x[7] = x[3]  # a duplicate: left-out point 3 still has an exact hit at 7
+    d, q = points(x, z, x, "hybrid", prec)
+    Z, _ = api.forward(d, q, p, prec, exclude_self=True)
+    Z = Z.cpu().numpy().astype(np.float64)
+    ref = oracle.forward(x, z, x, p, self_index=np.arange(len(x)))
+    assert np.max(scaled_err(Z, ref)) <= TOL[prec]
+    assert Z[3] == np.float64(z[7]).astype(np.float32 if prec == "f32" else np.float64)
+
+
+@pytest.mark.parametrize("split", [1, 3, 7, 64])
+def test_data_split_merges_to_the_same_result(split):
+    x, z, q = rand_case(9, 40000, 700, 2)
+    Z, _ = gpu_forward(x, z, q, 2.0, "aoas", "f32", split=split)
+    ref = oracle.forward(x, z, q, 2.0)
+    assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("qpl", [4, 8])
+def test_queries_per_lane_variants(qpl):
+    x, z, q = rand_case(10, 5000, 3000, 3)
+    Z, _ = gpu_forward(x, z, q, 3.0, "soa", "f32", queries_per_lane=qpl)
+    ref = oracle.forward(x, z, q, 3.0)
+    assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
+
+
+def test_tiny_and_degenerate_sizes():
+    for n, m in [(1, 1), (1, 5), (2, 1), (511, 3), (513, 257), (1024, 1)]:
+        x, z, q = rand_case(11 + n, n, m, 2)
+        Z, _ = gpu_forward(x, z, q, 2.0, "aos", "f32")
+        ref = oracle.forward(x, z, q, 2.0)
+        assert np.max(scaled_err(Z, ref)) <= TOL["f32"], (n, m)
+    # all data points at one location: extent is degenerate (taken as 1)
+    x = np.full((100, 2), 0.25)
+    z = np.arange(100.0)
+    q = np.array([[0.25, 0.25], [0.5, 0.5], [0.0, 1.0]])
+    Z, _ = gpu_forward(x, z, q, 2.0, "soa", "f32")
+    assert Z[0] == np.float32(np.mean(z))
+    np.testing.assert_allclose(Z[1:], np.mean(z), rtol=1e-6)
+
+
+def test_determinism_permutation_and_power_of_two_scaling():
+    x, z, q = rand_case(12, 6000, 2000, 2)
+    Z1, D1 = gpu_forward(x, z, q, 2.0, "aoas", "f32")
+    Z2, D2 = gpu_forward(x, z, q, 2.0, "aoas", "f32")
+    np.testing.assert_array_equal(Z1, Z2)
+    np.testing.assert_array_equal(D1, D2)
+    perm = np.random.default_rng(0).permutation(len(q))
+    Zp, _ = gpu_forward(x, z, q[perm], 2.0, "aoas", "f32")
+    np.testing.assert_array_equal(Zp, Z1[perm])
+    # coordinates times 2^5: the sweep rescales by a power of two, so Z is bit-identical
+    Zs, Ds = gpu_forward(x * 32.0, z, q * 32.0, 2.0, "aoas", "f32")
+    np.testing.assert_array_equal(Zs, Z1)
+    np.testing.assert_allclose(Ds, D1 / 1024.0, rtol=1e-15)
+
+
+def test_large_coordinates_and_offsets():
+    x, z, q = rand_case(13, 3000, 500, 2)
+    Z, _ = gpu_forward(x * 1e5 + 3e5, z, q * 1e5 + 3e5, 2.0, "aoas", "f64")
+    ref = oracle.forward(x * 1e5 + 3e5, z, q * 1e5 + 3e5, 2.0)
+    assert np.max(scaled_err(Z, ref)) <= TOL["f64"]
+    xs, qs = (x * 1e5).astype(np.float32).astype(np.float64), (q * 1e5).astype(np.float32).astype(np.float64)
+    Z, _ = gpu_forward(xs, z, qs, 6.0, "aoas", "f32")
+    ref = oracle.forward(xs, z, qs, 6.0)
+    assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
+
+
+def _sample(m, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(m, size=k, replace=False))
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos", "aoas"])
+def test_full_size_plain2d_1m_sampled(layout):
+    # The benchmark's workload (1,048,576 x 1,048,576, FP32, p = 2) in the benchmark's
+    # launch configuration; the oracle evaluates 192 sampled queries one by one.
+    cfg = workloads.WORKLOADS["plain2d_f32_1m"]
+    x, z, q, _ = workloads.plain2d(cfg["n"], cfg["m"], "f32", cfg=cfg["cfg"])
+    print(f"full-size plain2d layout={layout}", flush=True)
+    Z, D = gpu_forward(x, z, q, 2.0, layout, "f32")
+    idx = _sample(len(q), 192, 1)
+    ref = oracle.forward(x, z, q[idx], 2.0)
+    assert np.max(scaled_err(Z[idx], ref)) <= TOL["f32"]
+    np.testing.assert_allclose(D[idx], ref["D"], rtol=1e-5)
+    assert np.all(np.isfinite(Z))
+
+
+def test_full_size_mixture3d_hits_and_fp32_vs_fp64():
+    cfg = workloads.WORKLOADS["mixture3d_p2.5_262k_1m"]
+    x, z, q, hit_rows = workloads.mixture3d(cfg["n"], cfg["m"], cfg["hits"], "f32", cfg=cfg["cfg"])
+    print("full-size mixture3d", flush=True)
+    Z32, _ = gpu_forward(x, z, q, 2.5, "aoas", "f32")
+    Z64, _ = gpu_forward(x, z, q, 2.5, "aoas", "f64")
+    # every exact hit returns its data value
+    ref_h = oracle.forward(x, z, q[hit_rows], 2.5)
+    assert np.all(ref_h["H"] >= 1)
+    np.testing.assert_array_equal(Z32[hit_rows], ref_h["Z"].astype(np.float32).astype(np.float64))
+    np.testing.assert_array_equal(Z64[hit_rows], ref_h["Z"])
+    idx = _sample(len(q), 128, 2)
+    ref = oracle.forward(x, z, q[idx], 2.5)
+    assert np.max(scaled_err(Z32[idx], ref)) <= TOL["f32"]
+    assert np.max(scaled_err(Z64[idx], ref)) <= TOL["f64"]
+    # FP32 path against the GPU FP64 path for every query
+    rel = np.abs(Z32 - Z64) / np.maximum(np.abs(Z64), 1e-3)
+    assert np.max(rel) <= 1e-5

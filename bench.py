@@ -1,0 +1,202 @@
+"""Benchmark: Shepard IDW forward + adjoint at 1,048,576 x 1,048,576 FP32 (2-D, p = 2).
+
+One step = idw_forward (Eq. 1 over all pairs) + idw_backward (dL/dz, dL/dp, dL/dq) for a
+fixed synthetic upstream gradient, inputs resident in HBM.  Prints one JSON line:
+pairs/s over the timed steps, the roofline of the dominant sweep kernel (algorithmic FLOP
+per launch / its event-timed duration, against the FP32 vector peak), the FP32 error
+against the FP64 oracle on sampled queries, and the oracle's own rate on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--layout aoas] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "query×data pairs/sec, IDW fwd+bwd at 1M×1M FP32; % FP32 VALU peak; err vs FP64"
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 FLOP/clk/CU
+
+# Algorithmic FLOP per query x data pair, 2-D, p = 2 (add/sub/mul = 1, fma = 2,
+# transcendental = 1; compensation and bookkeeping not counted):
+#   forward     2 sub, mul + fma (r^2), rcp, fma (num), add (den)                  =  9
+#   query sweep 2 sub, mul + fma, rcp, log2, sub (z - Z), mul (t = w c), fma (P),
+#               mul (u = t / r^2, with 1/r^2 = w), 2 fma (G)                       = 16
+#   data sweep  2 sub, mul + fma, rcp, fma (dz)                                    =  8
+FLOP_PER_PAIR = {"fwd_sweep": 9, "bwd_query": 16, "bwd_data": 8}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1402_4986_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hpp", ".hip", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM traffic per launch measured with rocprofv3 counters (profiles/traffic.json),
+    only if the kernel sources are unchanged since the measurement."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(x, z, q, g, sample: int, Zgpu, dzgpu_unused=None):
+    """Times the FP64 oracle (forward + adjoint) on `sample` queries against all n data
+    points, single thread; returns (record, oracle outputs for the error report)."""
+    import numpy as np
+
+    import oracle
+    idx = np.sort(np.random.default_rng(99).choice(len(q), size=sample, replace=False))
+    t0 = time.perf_counter()
+    ref = oracle.forward(x, z, q[idx], 2.0)
+    oracle.backward(x, z, q[idx], 2.0, g[idx])
+    dt = time.perf_counter() - t0
+    pairs = float(sample) * len(x)
+    rec = {"value": pairs / dt, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+           "sample": f"{sample} seeded queries x all {len(x)} data points, forward + adjoint "
+                     f"(dz, dp, dq), FP64, one thread, {dt:.1f} s"}
+    return rec, idx, ref
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--layout", default="aoas", choices=["soa", "aos", "aoas", "hybrid", "soaos"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
+    ap.add_argument("--no-layouts", action="store_true", help="skip the per-layout forward timings")
+    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one device-to-device copy of 512 MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the sweep is measured on one GPU's share "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1402_4986_amd import _lib, api, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    cfg = workloads.WORKLOADS["plain2d_f32_1m"]
+    n, m, p = cfg["n"], cfg["m"], cfg["p"]
+    x, z, q, _ = workloads.plain2d(n, m, "f32", cfg=cfg["cfg"])
+    g = np.random.default_rng(7).normal(size=m).astype(np.float32).astype(np.float64)
+
+    def make(layout):
+        d = api.Points.from_arrays(workloads.pack_data(x, z, layout, "f32"), n, 2, layout, dev)
+        qq = api.Points.from_arrays(workloads.pack_query(q, layout, "f32"), m, 2, layout, dev)
+        return d, qq
+
+    data, query = make(args.layout)
+    gt = torch.tensor(g, dtype=torch.float32, device=dev)
+    ws = api.workspace(data, query, "f32")
+    Z = torch.empty(m, dtype=torch.float32, device=dev)
+    D = torch.empty(m, dtype=torch.float64, device=dev)
+
+    def step():
+        api.forward(data, query, p, "f32", out_z=Z, out_den=D, ws=ws)
+        return api.backward(data, query, p, gt, Z, D, "f32", ws=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _lib.check(lib.idw_timing_enable(1))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dz, dp, dq = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = {}
+    for name, which in (("fwd_sweep", _lib.T_FWD_SWEEP), ("bwd_query", _lib.T_BWD_QUERY),
+                        ("bwd_data", _lib.T_BWD_DATA)):
+        import ctypes
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        _lib.check(lib.idw_timing_read(which, ctypes.byref(ms), ctypes.byref(cnt)))
+        kt[name] = ms.value / max(cnt.value, 1)
+    _lib.check(lib.idw_timing_enable(0))
+
+    ms_step = wall * 1e3 / args.steps
+    pairs = float(n) * m
+    kernels = {}
+    for name, ms in kt.items():
+        tf = FLOP_PER_PAIR[name] * pairs / (ms * 1e-3) / 1e12
+        kernels[name] = {"ms": round(ms, 3), "tflops": round(tf, 2), "frac_of_peak": round(tf / PEAK_FP32_TFLOPS, 4)}
+    dom = max(kt, key=kt.get)
+    achieved = FLOP_PER_PAIR[dom] * pairs / (kt[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": load_traffic(dom)}
+    total_flop = sum(FLOP_PER_PAIR.values()) * pairs
+    out = {"metric": METRIC, "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "plain2d_f32_1m", "n_data": n, "n_query": m, "dim": 2, "p": p,
+                      "layout": args.layout, "precision": "fp32 sweep, fp64 ratio/fix-up",
+                      "grads": "dz,dp,dq"},
+           "frac_fp32_peak_step": round(total_flop / (ms_step * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+           "kernels": kernels, "roofline": roofline}
+
+    if args.calib_copy:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel() * 4
+        del src, dst
+
+    if not args.no_layouts:
+        lay = {}
+        for layout in ("soa", "aos", "aoas"):
+            d2, q2 = (data, query) if layout == args.layout else make(layout)
+            api.forward(d2, q2, p, "f32", out_z=Z, out_den=D, ws=ws)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(2):
+                api.forward(d2, q2, p, "f32", out_z=Z, out_den=D, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            lay[layout] = round(e0.elapsed_time(e1) / 2, 3)
+            del d2, q2
+        out["forward_ms_by_layout"] = lay
+        api.forward(data, query, p, "f32", out_z=Z, out_den=D, ws=ws)
+        torch.cuda.synchronize()
+
+    if not args.no_cpu:
+        Zh = Z.cpu().numpy().astype(np.float64)
+        rec, idx, ref = cpu_baseline(x, z, q, g, args.cpu_sample, Zh)
+        out["cpu_baseline"] = rec
+        err = np.abs(Zh[idx] - ref["Z"]) / ref["S"]
+        out["err_vs_fp64"] = {"max": float(err.max()), "median": float(np.median(err)),
+                              "metric": "|Z - Z_oracle| / (sum w|z| / sum w)",
+                              "sample": int(len(idx))}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -86,14 +86,20 @@ typedef struct idw_points {
 } idw_points;
 
 /* Optional launch configuration; zero fields select the library default.
- *   queries_per_lane  queries held in registers per lane of the sweep (FP32: 1,2,4,8;
- *                     FP64: 1,2,4)
+ *   queries_per_lane  queries held in registers per lane of the forward sweep (FP32: 4 or
+ *                     8; FP64: 2 or 4; default 4)
  *   split             number of data chunks swept by separate workgroups and merged in a
- *                     fixed order (1..1024); 0 = chosen from m so the chip is filled. */
+ *                     fixed order (1..1024); 0 = chosen from m so the chip is filled
+ *   batch_chunk       batched plans: data points per work item (rounded up to 512;
+ *                     default 16384)
+ *   batch_workgroups  batched plans: persistent workgroups (default 2 per compute unit)
+ *   reserved          must be zero */
 typedef struct idw_config {
   int32_t queries_per_lane;
   int32_t split;
-  int32_t reserved[6];
+  int32_t batch_chunk;
+  int32_t batch_workgroups;
+  int32_t reserved[4];
 } idw_config;
 
 /* Library version string (static storage). */
@@ -145,6 +151,19 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
                  const double* saved_den, void* grad_z, double* grad_p, void* grad_q,
                  void* workspace, size_t workspace_bytes, void* stream, const idw_config* cfg);
 
+/* ---- Kernel timing (benchmarks).  When enabled, idw_forward / idw_backward bracket each
+ * all-pairs sweep kernel with HIP events recorded on the launch stream.  Not for use
+ * under graph capture.  Host-side state is process-wide and mutex-protected. ---- */
+enum { IDW_T_FWD_SWEEP = 0, IDW_T_BWD_QUERY = 1, IDW_T_BWD_DATA = 2, IDW_T_COUNT = 3 };
+
+/* Enables (on != 0) or disables timing; either way drops pending events and resets the
+ * totals. */
+int idw_timing_enable(int32_t on);
+
+/* Waits for every recorded event, then returns the total milliseconds and launch count
+ * of sweep `which` (IDW_T_*) since the last idw_timing_enable. */
+int idw_timing_read(int32_t which, double* total_ms, int64_t* launches);
+
 /* ---- Batched form: many independent instances in one persistent launch. ---- */
 
 /* One instance: its own data, queries, p and outputs (device pointers). */
@@ -158,11 +177,13 @@ typedef struct idw_instance {
 
 typedef struct idw_plan idw_plan;
 
-/* Builds a plan for `count` instances (host descriptors, copied).  Only IDW_FP32 with
- * integer p in {1, 2, 3} or any p > 0 is accepted; every instance uses the IDW_AOAS layout
- * or any other layout (per instance).  The plan owns a device work list that it allocates
- * here (the only allocating entry point) and a HIP graph that is captured on the first
- * idw_batched call for a given workspace.  `cfg` may be NULL. */
+/* Builds a plan for `count` instances (host descriptors, copied; the device arrays they
+ * name must stay valid while the plan is used).  Precision IDW_FP32 only; every instance
+ * uses the IDW_AOAS layout for data and queries, has its own dim (2 or 3), p (any valid
+ * p; 1, 2 and 3 have fast forms) and sizes.  The sweep is the FP32 sweep of idw_forward
+ * with its FP64 ratio and FP64 fix-up of near-coincident queries.  The plan allocates its
+ * device work list here (the only allocating entry point) and captures a HIP graph on
+ * the first idw_batched call for a given workspace.  `cfg` may be NULL. */
 int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_t precision,
                             const idw_config* cfg, idw_plan** out_plan);
 

@@ -19,8 +19,9 @@ LAYOUT_CODES = {"soa": SOA, "aos": AOS, "aoas": AOAS, "hybrid": HYBRID, "soaos":
 PRECISION_CODES = {"f32": FP32, "f64": FP64}
 
 EXPORTED = ("idw_version", "idw_last_error", "idw_record_bytes", "idw_workspace_size",
-            "idw_forward", "idw_backward", "idw_batched_plan_create", "idw_batched_plan_workspace",
-            "idw_batched", "idw_batched_plan_destroy")
+            "idw_forward", "idw_backward", "idw_timing_enable", "idw_timing_read", "idw_batched_plan_create",
+            "idw_batched_plan_workspace", "idw_batched", "idw_batched_plan_destroy")
+T_FWD_SWEEP, T_BWD_QUERY, T_BWD_DATA = 0, 1, 2
 
 
 class IdwPoints(ctypes.Structure):
@@ -30,7 +31,8 @@ class IdwPoints(ctypes.Structure):
 
 class IdwConfig(ctypes.Structure):
     _fields_ = [("queries_per_lane", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("batch_chunk", ctypes.c_int32), ("batch_workgroups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class IdwInstance(ctypes.Structure):
@@ -74,6 +76,10 @@ def load(path: str | None = None):
         lib.idw_backward.restype = ctypes.c_int
         lib.idw_backward.argtypes = [P(IdwPoints), P(IdwPoints), ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
                                      vp, vp, vp, vp, vp, vp, vp, sz, vp, P(IdwConfig)]
+        lib.idw_timing_enable.restype = ctypes.c_int
+        lib.idw_timing_enable.argtypes = [ctypes.c_int32]
+        lib.idw_timing_read.restype = ctypes.c_int
+        lib.idw_timing_read.argtypes = [ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
         lib.idw_batched_plan_create.restype = ctypes.c_int
         lib.idw_batched_plan_create.argtypes = [P(IdwInstance), ctypes.c_int32, ctypes.c_int32, P(IdwConfig),
                                                 P(vp)]

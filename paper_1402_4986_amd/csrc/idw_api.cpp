@@ -9,6 +9,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/idw.h"
 #include "idw_api_internal.hpp"
@@ -178,12 +179,12 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   const bool f64 = precision == IDW_FP64;
   const int64_t n = data->n, m = query->n;
   // forward
-  w.qf = (cfg && cfg->queries_per_lane) ? cfg->queries_per_lane : (f64 ? 4 : 8);
+  w.qf = (cfg && cfg->queries_per_lane) ? cfg->queries_per_lane : 4;
   choose_split(n, cdiv(m, kWG * w.qf), cfg ? cfg->split : 0, w.split_f, w.chunk_f);
   // backward: query sweep over data chunks, data sweep over query chunks
-  w.qq = f64 ? 2 : 4;
+  w.qq = 2;
   choose_split(n, cdiv(m, kWG * w.qq), 0, w.split_q, w.chunk_q);
-  w.qz = f64 ? 2 : 8;
+  w.qz = f64 ? 2 : 4;
   choose_split(m > 0 ? m : 1, cdiv(n, kWG * w.qz), 0, w.split_z, w.chunk_z);
   w.nbbox = static_cast<int>(std::min<int64_t>(1024, cdiv(n, kWG)));
   w.nwg_dp = static_cast<int>(cdiv(m, kWG));
@@ -256,6 +257,56 @@ hipError_t enqueue_header(const idw_points* data, double p, bool f64, char* ws, 
                     reinterpret_cast<double*>(ws + w.hdr), st);
 }
 
+// ---- optional event timing of the sweep kernels ----
+struct TimingRec {
+  int which;
+  hipEvent_t a, b;
+};
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<TimingRec> g_pending;
+static double g_tot_ms[IDW_T_COUNT];
+static int64_t g_launches[IDW_T_COUNT];
+
+template <typename F>
+hipError_t timed(int which, hipStream_t st, F&& launch) {
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return launch();
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, st);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_pending.push_back({which, a, b});
+  return hipSuccess;
+}
+
+static int drain_timing(bool accumulate) {
+  int rc = IDW_OK;
+  for (auto& r : g_pending) {
+    if (accumulate && rc == IDW_OK) {
+      float ms = 0.f;
+      if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+        rc = fail(IDW_EDEVICE, "event timing failed");
+      g_tot_ms[r.which] += ms;
+      g_launches[r.which] += 1;
+    } else {
+      (void)hipEventSynchronize(r.b);
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_pending.clear();
+  return rc;
+}
+
 }  // namespace idw
 
 using namespace idw;
@@ -263,6 +314,28 @@ using namespace idw;
 extern "C" {
 
 const char* idw_version(void) { return "idw-gfx950 0.1.0"; }
+
+int idw_timing_enable(int32_t on) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  drain_timing(false);
+  for (int k = 0; k < IDW_T_COUNT; ++k) {
+    g_tot_ms[k] = 0.0;
+    g_launches[k] = 0;
+  }
+  g_timing = on != 0;
+  return IDW_OK;
+}
+
+int idw_timing_read(int32_t which, double* total_ms, int64_t* launches) {
+  clear_error();
+  if (which < 0 || which >= IDW_T_COUNT) return fail(IDW_EINVAL, "unknown timer %d", which);
+  std::lock_guard<std::mutex> lk(g_tmu);
+  const int rc = drain_timing(true);
+  if (total_ms) *total_ms = g_tot_ms[which];
+  if (launches) *launches = g_launches[which];
+  return rc;
+}
 
 const char* idw_last_error(void) { return g_err.c_str(); }
 
@@ -330,7 +403,8 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
 
   const LayoutFns& F = fns(data->layout);
   if ((rc = check_hip(enqueue_header(data, p, f64, ws, w, st), "extent kernels"))) return rc;
-  if ((rc = check_hip(F.fwd_sweep(a, f64, st), "forward sweep"))) return rc;
+  if ((rc = check_hip(timed(IDW_T_FWD_SWEEP, st, [&] { return F.fwd_sweep(a, f64, st); }), "forward sweep")))
+    return rc;
   if (a.split > 1 &&
       (rc = check_hip(merge_split(a.part, m, a.split, a.hdr, out_z, f64, out_den, a.flag, st), "merge")))
     return rc;
@@ -413,11 +487,13 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
                       "compaction")))
     return rc;
   if (ndp || ndq) {
-    if ((rc = check_hip(F.bwd_query(a, f64, st), "query sweep"))) return rc;
+    if ((rc = check_hip(timed(IDW_T_BWD_QUERY, st, [&] { return F.bwd_query(a, f64, st); }), "query sweep")))
+      return rc;
     if ((rc = check_hip(bwd_qmerge(a, f64, st), "query merge"))) return rc;
   }
   if (ndz) {
-    if ((rc = check_hip(F.bwd_data(a, f64, st), "data sweep"))) return rc;
+    if ((rc = check_hip(timed(IDW_T_BWD_DATA, st, [&] { return F.bwd_data(a, f64, st); }), "data sweep")))
+      return rc;
     if ((rc = check_hip(bwd_zmerge(a, f64, st), "data merge"))) return rc;
   }
   if ((rc = check_hip(F.bwd_fixup(a, f64, st), "FP64 fix-up"))) return rc;

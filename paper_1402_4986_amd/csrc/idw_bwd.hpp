@@ -27,51 +27,52 @@
 
 namespace idw {
 
-// w and, when needed, w / r2 and log2(r2), in the cheapest form for the weight class.
+// w, a factor f with w / r2 = w * f (when the position gradient is needed), and log2(r2)
+// (when the power gradient is needed), in the cheapest form for the weight class.
 template <int PM, bool NDQ, bool NDP>
-__device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& wr, float& lg) {
+__device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& f, float& lg) {
   if constexpr (PM == PM_GEN) {
     lg = __builtin_amdgcn_logf(r2);
     w = __builtin_amdgcn_exp2f(nhp * lg);
-    if constexpr (NDQ) wr = w * __builtin_amdgcn_rcpf(r2);
+    if constexpr (NDQ) f = __builtin_amdgcn_rcpf(r2);
   } else {
     if constexpr (NDP) lg = __builtin_amdgcn_logf(r2);
     if constexpr (PM == PM_2) {
       w = __builtin_amdgcn_rcpf(r2);
-      if constexpr (NDQ) wr = w * w;
+      if constexpr (NDQ) f = w;
     } else if constexpr (PM == PM_1) {
       w = __builtin_amdgcn_rsqf(r2);
-      if constexpr (NDQ) wr = w * w * w;
+      if constexpr (NDQ) f = w * w;
     } else if constexpr (PM == PM_3) {
       const float s = __builtin_amdgcn_rsqf(r2);
       const float s2 = s * s;
       w = s2 * s;
-      if constexpr (NDQ) wr = w * s2;
+      if constexpr (NDQ) f = s2;
     } else if constexpr (PM == PM_4) {
       const float t = __builtin_amdgcn_rcpf(r2);
       w = t * t;
-      if constexpr (NDQ) wr = w * t;
+      if constexpr (NDQ) f = t;
     } else {  // PM_25
       const float s = __builtin_amdgcn_rsqf(r2);
       const float s2 = s * s;
       w = s2 * __builtin_amdgcn_sqrtf(s);
-      if constexpr (NDQ) wr = w * s2;
+      if constexpr (NDQ) f = s2;
     }
   }
 }
 
 template <int PM, bool NDQ, bool NDP>
-__device__ __forceinline__ void wterms(double r2, double nhp, double& w, double& wr, double& lg) {
+__device__ __forceinline__ void wterms(double r2, double nhp, double& w, double& f, double& lg) {
   if constexpr (NDP || PM == PM_GEN) lg = log2(r2);
   if constexpr (PM == PM_GEN)
     w = exp2(nhp * lg);
   else
     w = weight<PM>(r2, nhp);
-  if constexpr (NDQ) wr = w / r2;
+  if constexpr (NDQ) f = 1.0 / r2;
 }
 
 // One LDS tile of the query sweep.  `cnt` records are valid (all of them unless TAIL).
-template <typename T, int DIM, int PM, int Q, bool DIAG, bool TAIL, bool NDP, bool NDQ>
+template <typename T, int DIM, int PM, int Q, bool DIAG, bool TAIL, bool NDP, bool NDQ, int UNR>
 __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt, int64_t jt,
                                           const T (&qc)[Q][3], const T (&zq)[Q],
                                           const int64_t (&qi)[Q], T nhp, T (&ph)[Q], T (&pl)[Q],
@@ -86,7 +87,7 @@ __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt,
       ag[k][0] = ag[k][1] = ag[k][2] = T(0);
     }
     const int ce = TAIL ? ((lim - c0) < CH ? (lim - c0) : CH) : CH;
-#pragma unroll 2
+#pragma unroll UNR
     for (int jj = 0; jj < ce; ++jj) {
       const P4<T> d = tl[c0 + jj];
       const T dv = (DIM == 3) ? d.w : d.z;
@@ -108,11 +109,12 @@ __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt,
             c = T(0);
           }
         }
-        T w, wr = T(0), lg = T(0);
-        wterms<PM, NDQ, NDP>(r2, nhp, w, wr, lg);
-        if constexpr (NDP) ap[k] = fmaT(w * c, lg, ap[k]);
+        T w, f = T(0), lg = T(0);
+        wterms<PM, NDQ, NDP>(r2, nhp, w, f, lg);
+        const T t = w * c;
+        if constexpr (NDP) ap[k] = fmaT(t, lg, ap[k]);
         if constexpr (NDQ) {
-          const T u = c * wr;
+          const T u = t * f;  // (w / r2) (z - Z)
           ag[k][0] = fmaT(u, dx, ag[k][0]);
           ag[k][1] = fmaT(u, dy, ag[k][1]);
           if constexpr (DIM == 3) ag[k][2] = fmaT(u, dz, ag[k][2]);
@@ -131,8 +133,17 @@ __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt,
 }
 
 // Query sweep: writes part[c * m + i] = (P, Gx, Gy, Gz) in scaled units (double).
-template <typename T, int DIM, int L, int PM, int Q, bool NDP, bool NDQ>
-__global__ __launch_bounds__(kWG) void k_bwd_query(DevPts data, int64_t n, DevPts query, int64_t m,
+// Measured on MI355X: FP32 Q = 2, unroll 4, >= 2 waves per SIMD (13.8 lane-slots per pair
+// for 2-D p = 2 with dp and dq, against 14.6 for Q = 4).
+template <typename T, int Q>
+struct QueryTune {
+  static constexpr int UNR = 4;
+  static constexpr int WPE = (Q <= 2) ? 2 : 1;
+};
+
+template <typename T, int DIM, int L, int PM, int Q, bool NDP, bool NDQ,
+          int UNR = QueryTune<T, Q>::UNR, int WPE = QueryTune<T, Q>::WPE>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_query(DevPts data, int64_t n, DevPts query, int64_t m,
                                                    int64_t chunk, T nhp, unsigned flags,
                                                    const double* __restrict__ hdr,
                                                    const T* __restrict__ saved_z,
@@ -193,14 +204,14 @@ __global__ __launch_bounds__(kWG) void k_bwd_query(DevPts data, int64_t n, DevPt
     const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
     if (cnt < kTile) {
       if (diag)
-        bwdq_tile<T, DIM, PM, Q, true, true, NDP, NDQ>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+        bwdq_tile<T, DIM, PM, Q, true, true, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
       else
-        bwdq_tile<T, DIM, PM, Q, false, true, NDP, NDQ>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+        bwdq_tile<T, DIM, PM, Q, false, true, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
     } else {
       if (diag)
-        bwdq_tile<T, DIM, PM, Q, true, false, NDP, NDQ>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+        bwdq_tile<T, DIM, PM, Q, true, false, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
       else
-        bwdq_tile<T, DIM, PM, Q, false, false, NDP, NDQ>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+        bwdq_tile<T, DIM, PM, Q, false, false, NDP, NDQ, UNR>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
     }
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
@@ -258,7 +269,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_qmerge(const double4* __restrict__ 
 }
 
 // One LDS tile of the data sweep: for the lane's Q data points, accumulate a_i * w_ij.
-template <typename T, int DIM, int PM, int Q, bool DIAG>
+template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR>
 __device__ __forceinline__ void bwdd_tile(const P4<T>* __restrict__ tl, int64_t it,
                                           const T (&xc)[Q][3], const int64_t (&xj)[Q], T nhp,
                                           T (&zh)[Q], T (&zl)[Q]) {
@@ -267,7 +278,7 @@ __device__ __forceinline__ void bwdd_tile(const P4<T>* __restrict__ tl, int64_t 
     T az[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) az[k] = T(0);
-#pragma unroll 4
+#pragma unroll UNR
     for (int ii = 0; ii < CH; ++ii) {
       const P4<T> d = tl[c0 + ii];
       const T a = (DIM == 3) ? d.w : d.z;
@@ -287,8 +298,16 @@ __device__ __forceinline__ void bwdd_tile(const P4<T>* __restrict__ tl, int64_t 
 }
 
 // Data sweep: part[c * n + j] = sum over query chunk c of a_i w_ij (double).
-template <typename T, int DIM, int L, int PM, int Q>
-__global__ __launch_bounds__(kWG) void k_bwd_data(DevPts data, int64_t n, DevPts query, int64_t m,
+// Measured on MI355X: FP32 Q = 4, unroll 4, >= 2 waves per SIMD (6.8 lane-slots per pair).
+template <typename T, int Q>
+struct DataTune {
+  static constexpr int UNR = 4;
+  static constexpr int WPE = 2;
+};
+
+template <typename T, int DIM, int L, int PM, int Q, int UNR = DataTune<T, Q>::UNR,
+          int WPE = DataTune<T, Q>::WPE>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_data(DevPts data, int64_t n, DevPts query, int64_t m,
                                                   int64_t chunk, T nhp, unsigned flags,
                                                   const double* __restrict__ hdr,
                                                   const T* __restrict__ grad_out,
@@ -351,9 +370,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_data(DevPts data, int64_t n, DevPts
     const int64_t it = ib + static_cast<int64_t>(t) * kTile;
     const bool diag = excl && it < x0 + kWG * Q && x0 < it + kTile;
     if (diag)
-      bwdd_tile<T, DIM, PM, Q, true>(tile[t & 1], it, xc, xj, nhp, zh, zl);
+      bwdd_tile<T, DIM, PM, Q, true, 1>(tile[t & 1], it, xc, xj, nhp, zh, zl);
     else
-      bwdd_tile<T, DIM, PM, Q, false>(tile[t & 1], it, xc, xj, nhp, zh, zl);
+      bwdd_tile<T, DIM, PM, Q, false, UNR>(tile[t & 1], it, xc, xj, nhp, zh, zl);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }

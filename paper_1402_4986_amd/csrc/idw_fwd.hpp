@@ -61,7 +61,7 @@ __device__ __forceinline__ P4<T> stage(const T (&c)[3], T v, T s) {
 }
 
 // Consume one LDS tile: for each of the lane's Q queries, accumulate w*z and w.
-template <typename T, int DIM, int PM, int Q, bool DIAG>
+template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR>
 __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t jt,
                                          const T (&qc)[Q][3], const int64_t (&qi)[Q], T nhp,
                                          T (&nh)[Q], T (&nl)[Q], T (&dh)[Q], T (&dl)[Q]) {
@@ -73,7 +73,7 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
       an[k] = T(0);
       ad[k] = T(0);
     }
-#pragma unroll 4
+#pragma unroll UNR
     for (int jj = 0; jj < CH; ++jj) {
       const P4<T> d = tl[c0 + jj];
       const T dv = (DIM == 3) ? d.w : d.z;
@@ -107,8 +107,19 @@ __device__ __forceinline__ void fwd_finish(int64_t i, double num, double den, co
   out_flag[i] = ok ? 0 : 1;
 }
 
-template <typename T, int DIM, int L, int PM, int Q>
-__global__ __launch_bounds__(kWG) void k_fwd_sweep(DevPts data, int64_t n, DevPts query, int64_t m,
+// Register-blocking and occupancy knobs of a sweep kernel: UNR = unroll of the per-record
+// loop, WPE = minimum waves per SIMD the register allocation must allow.
+// Values measured on MI355X (1M queries x 128K data, 2-D, p = 2): FP32 Q = 4 with a 4-deep
+// unroll issues 7.4 VALU lane-slots per pair against 8.3 for Q = 8.
+template <typename T, int Q>
+struct SweepTune {
+  static constexpr int UNR = (Q >= 8) ? 2 : 4;
+  static constexpr int WPE = 1;
+};
+
+template <typename T, int DIM, int L, int PM, int Q, int UNR = SweepTune<T, Q>::UNR,
+          int WPE = SweepTune<T, Q>::WPE>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_fwd_sweep(DevPts data, int64_t n, DevPts query, int64_t m,
                                                    int64_t chunk, int split, T nhp, unsigned flags,
                                                    const double* __restrict__ hdr,
                                                    T* __restrict__ out_z,
@@ -164,9 +175,9 @@ __global__ __launch_bounds__(kWG) void k_fwd_sweep(DevPts data, int64_t n, DevPt
     const int64_t jt = jb + static_cast<int64_t>(t) * kTile;
     const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
     if (diag)
-      fwd_tile<T, DIM, PM, Q, true>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
+      fwd_tile<T, DIM, PM, Q, true, 1>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
     else
-      fwd_tile<T, DIM, PM, Q, false>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
+      fwd_tile<T, DIM, PM, Q, false, UNR>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }

@@ -206,6 +206,10 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   w.slot_coef = take(sizeof(double) * static_cast<size_t>(m));
   w.slot_hits = take(sizeof(int) * static_cast<size_t>(m));
   w.slot_dp = take(sizeof(double) * static_cast<size_t>(m));
+  w.slot_z = take(sizeof(double) * static_cast<size_t>(m));
+  w.slot_den = take(sizeof(double) * static_cast<size_t>(m));
+  w.fpart = take(sizeof(double4) * kFixGrid);
+  w.fix_cmax = static_cast<int>(std::min<int64_t>(kFixGrid, std::max<int64_t>(1, cdiv(n, 4096))));
   w.wg_dp = take(sizeof(double) * static_cast<size_t>(w.nwg_dp > 0 ? w.nwg_dp : 1));
   w.total = off;
   (void)f64;
@@ -400,6 +404,8 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   a.part = reinterpret_cast<double2*>(ws + w.part_f);
   a.list = reinterpret_cast<const int*>(ws + w.list);
   a.count = reinterpret_cast<const int*>(ws + w.hdr + 256);
+  a.fix_cmax = w.fix_cmax;
+  a.fpart = reinterpret_cast<double4*>(ws + w.fpart);
 
   const LayoutFns& F = fns(data->layout);
   if ((rc = check_hip(enqueue_header(data, p, f64, ws, w, st), "extent kernels"))) return rc;
@@ -476,6 +482,10 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
   a.slot_coef = reinterpret_cast<double*>(ws + w.slot_coef);
   a.slot_hits = reinterpret_cast<int*>(ws + w.slot_hits);
   a.slot_dp = reinterpret_cast<double*>(ws + w.slot_dp);
+  a.slot_z = reinterpret_cast<double*>(ws + w.slot_z);
+  a.slot_den = reinterpret_cast<double*>(ws + w.slot_den);
+  a.fix_cmax = w.fix_cmax;
+  a.fpart = reinterpret_cast<double4*>(ws + w.fpart);
 
   const LayoutFns& F = fns(data->layout);
   uint8_t* flag = reinterpret_cast<uint8_t*>(ws + w.flag);

@@ -393,76 +393,173 @@ __global__ __launch_bounds__(kWG) void k_bwd_zmerge(const double* __restrict__ p
   grad_z[j] = static_cast<T>(h + l);
 }
 
-// FP64 per-query fix-up of the adjoint for flagged queries (one workgroup per query).
+// FP64 fix-up of the adjoint for flagged queries (exact hits and near-coincident points),
+// in two passes over the data, each cut into chunks as in k_fwd_fixup:
+//   pass 1: D, Z and the hit count of each flagged query;
+//   pass 2: P = sum w (1/2) ln(r2) (z - Z) and G = sum (w / r2)(z - Z)(q - x) for the
+//           flagged queries without a hit.
+// Per slot it leaves the dz coefficient (g / D, or g / h at a hit) and hit count for
+// k_bwd_fixz, the dp contribution, and writes dq for its query.
+template <typename T>
+__device__ __forceinline__ void bwd_fix1_finish(int sl, int64_t i, double num, double den, double h, int dim,
+                                                const T* __restrict__ grad_out, T* __restrict__ grad_q,
+                                                double* __restrict__ slot_coef, int* __restrict__ slot_hits,
+                                                double* __restrict__ slot_dp, double* __restrict__ slot_z,
+                                                double* __restrict__ slot_den) {
+  const double g = static_cast<double>(grad_out[i]);
+  if (h > 0.0) {
+    slot_coef[sl] = g / h;
+    slot_hits[sl] = static_cast<int>(h);
+    slot_dp[sl] = 0.0;
+    if (grad_q)
+      for (int d = 0; d < dim; ++d) grad_q[i * dim + d] = T(0);
+  } else {
+    slot_z[sl] = num / den;
+    slot_den[sl] = den;
+    slot_coef[sl] = g / den;
+    slot_hits[sl] = 0;
+  }
+}
+
 template <typename T, int DIM, int L, int PM>
-__global__ __launch_bounds__(kWG) void k_bwd_fixq(DevPts data, int64_t n, DevPts query, double p,
+__global__ __launch_bounds__(kWG) void k_bwd_fix1(DevPts data, int64_t n, DevPts query, double p,
                                                   unsigned flags, const int* __restrict__ list,
-                                                  const int* __restrict__ count,
-                                                  const T* __restrict__ grad_out,
-                                                  T* __restrict__ grad_q,
-                                                  double* __restrict__ slot_coef,
-                                                  int* __restrict__ slot_hits,
-                                                  double* __restrict__ slot_dp) {
+                                                  const int* __restrict__ count, int cmax,
+                                                  double4* __restrict__ fpart,
+                                                  const T* __restrict__ grad_out, T* __restrict__ grad_q,
+                                                  double* __restrict__ slot_coef, int* __restrict__ slot_hits,
+                                                  double* __restrict__ slot_dp, double* __restrict__ slot_z,
+                                                  double* __restrict__ slot_den) {
   __shared__ double red[kWG];
   __shared__ long long redi[kWG];
   const int cnt = *count;
+  const int C = fix_chunks(cnt, cmax);
+  const int64_t total = static_cast<int64_t>(cnt) * C;
+  const int64_t len = C > 0 ? (n + C - 1) / C : 0;
   const bool excl = (flags & 1u) != 0;
   const double nhp = -0.5 * p;
-  for (int sl = blockIdx.x; sl < cnt; sl += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int sl = static_cast<int>(w / C);
+    const int64_t c = w % C;
     const int64_t i = list[sl];
+    const int64_t j0 = c * len;
+    const int64_t j1 = (j0 + len < n) ? j0 + len : n;
     T qt[3] = {T(0), T(0), T(0)};
     Loader<T, DIM, L>::query(query, i, qt);
-    double q[3] = {static_cast<double>(qt[0]), static_cast<double>(qt[1]), static_cast<double>(qt[2])};
     NSum num, den;
     long long h = 0;
-    for (int64_t j = threadIdx.x; j < n; j += kWG) {
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kWG) {
       if (excl && j == i) continue;
-      T c[3] = {T(0), T(0), T(0)}, v;
-      Loader<T, DIM, L>::data(data, j, c, v);
+      T cc[3] = {T(0), T(0), T(0)}, v;
+      Loader<T, DIM, L>::data(data, j, cc, v);
       double r2 = 0.0;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const double e = q[d] - static_cast<double>(c[d]);
+        const double e = static_cast<double>(qt[d]) - static_cast<double>(cc[d]);
         r2 += e * e;
       }
       if (r2 == 0.0) {
         ++h;
       } else {
-        const double w = weight<PM>(r2, nhp);
-        num.add(w * static_cast<double>(v));
-        den.add(w);
+        const double wgt = weight<PM>(r2, nhp);
+        num.add(wgt * static_cast<double>(v));
+        den.add(wgt);
       }
     }
     const double tn = block_sum(num.value(), red);
     const double td = block_sum(den.value(), red);
     const long long th = block_sum_i64(h, redi);
-    const double g = static_cast<double>(grad_out[i]);
-    if (th > 0) {
-      if (threadIdx.x == 0) {
-        slot_coef[sl] = g / static_cast<double>(th);
-        slot_hits[sl] = static_cast<int>(th);
-        slot_dp[sl] = 0.0;
-        if (grad_q)
-          for (int d = 0; d < DIM; ++d) grad_q[i * DIM + d] = T(0);
-      }
-      continue;
+    if (threadIdx.x == 0) {
+      if (C == 1)
+        bwd_fix1_finish<T>(sl, i, tn, td, static_cast<double>(th), DIM, grad_out, grad_q, slot_coef,
+                           slot_hits, slot_dp, slot_z, slot_den);
+      else
+        fpart[w] = make_double4(tn, td, 0.0, static_cast<double>(th));
     }
-    const double Z = tn / td;
+  }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kWG) void k_bwd_fix1_merge(const int* __restrict__ list,
+                                                        const int* __restrict__ count, int cmax,
+                                                        const double4* __restrict__ fpart,
+                                                        const T* __restrict__ grad_out, T* __restrict__ grad_q,
+                                                        double* __restrict__ slot_coef,
+                                                        int* __restrict__ slot_hits,
+                                                        double* __restrict__ slot_dp,
+                                                        double* __restrict__ slot_z,
+                                                        double* __restrict__ slot_den) {
+  const int cnt = *count;
+  const int C = fix_chunks(cnt, cmax);
+  if (C <= 1) return;
+  for (int sl = blockIdx.x * kWG + threadIdx.x; sl < cnt; sl += gridDim.x * kWG) {
+    double nh = 0.0, nl = 0.0, dh = 0.0, dl = 0.0, h = 0.0;
+    for (int c = 0; c < C; ++c) {
+      const double4 v = fpart[static_cast<int64_t>(sl) * C + c];
+      two_sum_acc(nh, nl, v.x);
+      two_sum_acc(dh, dl, v.y);
+      h += v.w;
+    }
+    bwd_fix1_finish<T>(sl, list[sl], nh + nl, dh + dl, h, DIM, grad_out, grad_q, slot_coef, slot_hits,
+                       slot_dp, slot_z, slot_den);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bwd_fix2_finish(int sl, int64_t i, double P, const double (&G)[3], int dim,
+                                                double p, const T* __restrict__ grad_out,
+                                                T* __restrict__ grad_q, double* __restrict__ slot_dp,
+                                                const double* __restrict__ slot_den) {
+  const double g = static_cast<double>(grad_out[i]);
+  const double D = slot_den[sl];
+  slot_dp[sl] = -(g / D) * P;
+  if (grad_q)
+    for (int d = 0; d < dim; ++d) grad_q[i * dim + d] = static_cast<T>(-(p * g / D) * G[d]);
+}
+
+template <typename T, int DIM, int L, int PM>
+__global__ __launch_bounds__(kWG) void k_bwd_fix2(DevPts data, int64_t n, DevPts query, double p,
+                                                  unsigned flags, const int* __restrict__ list,
+                                                  const int* __restrict__ count, int cmax,
+                                                  double4* __restrict__ fpart,
+                                                  const T* __restrict__ grad_out, T* __restrict__ grad_q,
+                                                  const int* __restrict__ slot_hits,
+                                                  double* __restrict__ slot_dp,
+                                                  const double* __restrict__ slot_z,
+                                                  const double* __restrict__ slot_den) {
+  __shared__ double red[kWG];
+  const int cnt = *count;
+  const int C = fix_chunks(cnt, cmax);
+  const int64_t total = static_cast<int64_t>(cnt) * C;
+  const int64_t len = C > 0 ? (n + C - 1) / C : 0;
+  const bool excl = (flags & 1u) != 0;
+  const double nhp = -0.5 * p;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int sl = static_cast<int>(w / C);
+    if (slot_hits[sl] > 0) continue;  // uniform over the workgroup
+    const int64_t c = w % C;
+    const int64_t i = list[sl];
+    const int64_t j0 = c * len;
+    const int64_t j1 = (j0 + len < n) ? j0 + len : n;
+    const double Z = slot_z[sl];
+    T qt[3] = {T(0), T(0), T(0)};
+    Loader<T, DIM, L>::query(query, i, qt);
+    const double q[3] = {static_cast<double>(qt[0]), static_cast<double>(qt[1]), static_cast<double>(qt[2])};
     NSum P, G[3];
-    for (int64_t j = threadIdx.x; j < n; j += kWG) {
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kWG) {
       if (excl && j == i) continue;
-      T c[3] = {T(0), T(0), T(0)}, v;
-      Loader<T, DIM, L>::data(data, j, c, v);
+      T cc[3] = {T(0), T(0), T(0)}, v;
+      Loader<T, DIM, L>::data(data, j, cc, v);
       double e[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        e[d] = q[d] - static_cast<double>(c[d]);
+        e[d] = q[d] - static_cast<double>(cc[d]);
         r2 += e[d] * e[d];
       }
-      const double w = weight<PM>(r2, nhp);
+      const double wgt = weight<PM>(r2, nhp);
       const double cz = static_cast<double>(v) - Z;
-      P.add(w * 0.5 * log(r2) * cz);
-      const double u = (w / r2) * cz;
+      P.add(wgt * 0.5 * log(r2) * cz);
+      const double u = (wgt / r2) * cz;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) G[d].add(u * e[d]);
     }
@@ -470,12 +567,37 @@ __global__ __launch_bounds__(kWG) void k_bwd_fixq(DevPts data, int64_t n, DevPts
     double tG[3] = {0.0, 0.0, 0.0};
     for (int d = 0; d < DIM; ++d) tG[d] = block_sum(G[d].value(), red);
     if (threadIdx.x == 0) {
-      slot_coef[sl] = g / td;
-      slot_hits[sl] = 0;
-      slot_dp[sl] = -(g / td) * tP;
-      if (grad_q)
-        for (int d = 0; d < DIM; ++d) grad_q[i * DIM + d] = static_cast<T>(-(p * g / td) * tG[d]);
+      if (C == 1)
+        bwd_fix2_finish<T>(sl, i, tP, tG, DIM, p, grad_out, grad_q, slot_dp, slot_den);
+      else
+        fpart[w] = make_double4(tP, tG[0], tG[1], tG[2]);
     }
+  }
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kWG) void k_bwd_fix2_merge(const int* __restrict__ list,
+                                                        const int* __restrict__ count, int cmax,
+                                                        const double4* __restrict__ fpart, double p,
+                                                        const T* __restrict__ grad_out, T* __restrict__ grad_q,
+                                                        const int* __restrict__ slot_hits,
+                                                        double* __restrict__ slot_dp,
+                                                        const double* __restrict__ slot_den) {
+  const int cnt = *count;
+  const int C = fix_chunks(cnt, cmax);
+  if (C <= 1) return;
+  for (int sl = blockIdx.x * kWG + threadIdx.x; sl < cnt; sl += gridDim.x * kWG) {
+    if (slot_hits[sl] > 0) continue;
+    double P[2] = {0.0, 0.0}, G[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int c = 0; c < C; ++c) {
+      const double4 v = fpart[static_cast<int64_t>(sl) * C + c];
+      two_sum_acc(P[0], P[1], v.x);
+      two_sum_acc(G[0][0], G[0][1], v.y);
+      two_sum_acc(G[1][0], G[1][1], v.z);
+      two_sum_acc(G[2][0], G[2][1], v.w);
+    }
+    const double g3[3] = {G[0][0] + G[0][1], G[1][0] + G[1][1], G[2][0] + G[2][1]};
+    bwd_fix2_finish<T>(sl, list[sl], P[0] + P[1], g3, DIM, p, grad_out, grad_q, slot_dp, slot_den);
   }
 }
 
@@ -593,9 +715,19 @@ hipError_t launch_bwd_data_t(const BwdArgs& a, int split, int64_t chunk, double*
 template <typename T, int DIM, int L, int PM>
 hipError_t launch_bwd_fix_t(const BwdArgs& a, hipStream_t st) {
   const T* go = static_cast<const T*>(a.grad_out);
-  hipLaunchKernelGGL((k_bwd_fixq<T, DIM, L, PM>), dim3(a.fix_grid), dim3(kWG), 0, st, a.data,
-                     a.n, a.query, a.p, a.flags, a.list, a.count, go, static_cast<T*>(a.grad_q),
-                     a.slot_coef, a.slot_hits, a.slot_dp);
+  T* gq = static_cast<T*>(a.grad_q);
+  hipLaunchKernelGGL((k_bwd_fix1<T, DIM, L, PM>), dim3(kFixGrid), dim3(kWG), 0, st, a.data, a.n, a.query,
+                     a.p, a.flags, a.list, a.count, a.fix_cmax, a.fpart, go, gq, a.slot_coef, a.slot_hits,
+                     a.slot_dp, a.slot_z, a.slot_den);
+  hipLaunchKernelGGL((k_bwd_fix1_merge<T, DIM>), dim3(4), dim3(kWG), 0, st, a.list, a.count, a.fix_cmax,
+                     a.fpart, go, gq, a.slot_coef, a.slot_hits, a.slot_dp, a.slot_z, a.slot_den);
+  if (a.flags & 0xcu) {  // dp or dq requested
+    hipLaunchKernelGGL((k_bwd_fix2<T, DIM, L, PM>), dim3(kFixGrid), dim3(kWG), 0, st, a.data, a.n, a.query,
+                       a.p, a.flags, a.list, a.count, a.fix_cmax, a.fpart, go, gq, a.slot_hits, a.slot_dp,
+                       a.slot_z, a.slot_den);
+    hipLaunchKernelGGL((k_bwd_fix2_merge<T, DIM>), dim3(4), dim3(kWG), 0, st, a.list, a.count, a.fix_cmax,
+                       a.fpart, a.p, go, gq, a.slot_hits, a.slot_dp, a.slot_den);
+  }
   if (a.grad_z)
     hipLaunchKernelGGL((k_bwd_fixz<T, DIM, L, PM>),
                        dim3(static_cast<unsigned>((a.n + kWG - 1) / kWG)), dim3(kWG), 0, st,

@@ -195,45 +195,64 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
   }
 }
 
-// FP64 recomputation of flagged queries: one workgroup per query, data strided over the
-// workgroup's lanes (ceil(n / 256) records per lane), exact d == 0 detection, Neumaier
-// sums per lane and a fixed-order tree reduction.  Writes Z and D (caller units; +inf
-// for an exact hit, whose Z is the mean of the coincident values).
+// FP64 recomputation of flagged queries.  The pattern of the improved CDP version
+// (Section 3.1): a block of threads strides over the data points of one query with
+// ceil(len / 256) points per lane, then a block reduction.  When few queries are flagged,
+// each query's data range is cut into C chunks swept by different workgroups (C from the
+// flagged count, so the grid of kFixGrid workgroups stays busy); chunk partials are
+// merged in chunk order by k_fwd_fixmerge.  Exact d == 0 detection, Neumaier sums per lane,
+// fixed-order tree reductions.  Writes Z and D (caller units; +inf at an exact hit, whose
+// Z is the mean of the coincident values).
+__device__ __forceinline__ int fix_chunks(int cnt, int cmax) {
+  if (cnt <= 0) return 0;
+  int c = kFixGrid / cnt;
+  if (c > cmax) c = cmax;
+  return c < 1 ? 1 : c;
+}
+
 template <typename T, int DIM, int L, int PM>
 __global__ __launch_bounds__(kWG) void k_fwd_fixup(DevPts data, int64_t n, DevPts query,
                                                    double nhp, unsigned flags,
                                                    const int* __restrict__ list,
-                                                   const int* __restrict__ count,
+                                                   const int* __restrict__ count, int cmax,
+                                                   double4* __restrict__ fpart,
                                                    T* __restrict__ out_z,
                                                    double* __restrict__ out_den) {
   __shared__ double red[kWG];
   __shared__ long long redi[kWG];
   const int cnt = *count;
+  const int C = fix_chunks(cnt, cmax);
+  const int64_t total = static_cast<int64_t>(cnt) * C;
+  const int64_t len = C > 0 ? (n + C - 1) / C : 0;
   const bool excl = (flags & 1u) != 0;
-  for (int sl = blockIdx.x; sl < cnt; sl += gridDim.x) {
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int sl = static_cast<int>(w / C);
+    const int64_t c = w % C;
     const int64_t i = list[sl];
+    const int64_t j0 = c * len;
+    const int64_t j1 = (j0 + len < n) ? j0 + len : n;
     T qt[3] = {T(0), T(0), T(0)};
     Loader<T, DIM, L>::query(query, i, qt);
     NSum num, den;
     double hz = 0.0;
     long long h = 0;
-    for (int64_t j = threadIdx.x; j < n; j += kWG) {
+    for (int64_t j = j0 + threadIdx.x; j < j1; j += kWG) {
       if (excl && j == i) continue;
-      T c[3] = {T(0), T(0), T(0)}, v;
-      Loader<T, DIM, L>::data(data, j, c, v);
+      T cc[3] = {T(0), T(0), T(0)}, v;
+      Loader<T, DIM, L>::data(data, j, cc, v);
       double r2 = 0.0;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        const double e = static_cast<double>(qt[d]) - static_cast<double>(c[d]);
+        const double e = static_cast<double>(qt[d]) - static_cast<double>(cc[d]);
         r2 += e * e;
       }
       if (r2 == 0.0) {
         ++h;
         hz += static_cast<double>(v);
       } else {
-        const double w = weight<PM>(r2, nhp);
-        num.add(w * static_cast<double>(v));
-        den.add(w);
+        const double wgt = weight<PM>(r2, nhp);
+        num.add(wgt * static_cast<double>(v));
+        den.add(wgt);
       }
     }
     const double tn = block_sum(num.value(), red);
@@ -241,10 +260,40 @@ __global__ __launch_bounds__(kWG) void k_fwd_fixup(DevPts data, int64_t n, DevPt
     const double thz = block_sum(hz, red);
     const long long th = block_sum_i64(h, redi);
     if (threadIdx.x == 0) {
-      const double Z = th > 0 ? thz / static_cast<double>(th) : tn / td;
-      out_z[i] = static_cast<T>(Z);
-      if (out_den) out_den[i] = th > 0 ? __builtin_huge_val() : td;
+      if (C == 1) {
+        const double Z = th > 0 ? thz / static_cast<double>(th) : tn / td;
+        out_z[i] = static_cast<T>(Z);
+        if (out_den) out_den[i] = th > 0 ? __builtin_huge_val() : td;
+      } else {
+        fpart[w] = make_double4(tn, td, thz, static_cast<double>(th));
+      }
     }
+  }
+}
+
+// Merges the chunk partials of split fix-up queries (chunk order, TwoSum) and finalises.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_fwd_fixmerge(const int* __restrict__ list,
+                                                      const int* __restrict__ count, int cmax,
+                                                      const double4* __restrict__ fpart,
+                                                      T* __restrict__ out_z,
+                                                      double* __restrict__ out_den) {
+  const int cnt = *count;
+  const int C = fix_chunks(cnt, cmax);
+  if (C <= 1) return;
+  for (int sl = blockIdx.x * kWG + threadIdx.x; sl < cnt; sl += gridDim.x * kWG) {
+    double nh = 0.0, nl = 0.0, dh = 0.0, dl = 0.0, hz = 0.0, h = 0.0;
+    for (int c = 0; c < C; ++c) {
+      const double4 v = fpart[static_cast<int64_t>(sl) * C + c];
+      two_sum_acc(nh, nl, v.x);
+      two_sum_acc(dh, dl, v.y);
+      hz += v.z;
+      h += v.w;
+    }
+    const int64_t i = list[sl];
+    const double Z = h > 0.0 ? hz / h : (nh + nl) / (dh + dl);
+    out_z[i] = static_cast<T>(Z);
+    if (out_den) out_den[i] = h > 0.0 ? __builtin_huge_val() : dh + dl;
   }
 }
 
@@ -334,9 +383,11 @@ hipError_t launch_fwd_sweep(const FwdArgs& a, bool f64, hipStream_t st) {
 
 template <typename T, int DIM, int L, int PM>
 hipError_t launch_fwd_fixup_t(const FwdArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_fwd_fixup<T, DIM, L, PM>), dim3(a.fix_grid), dim3(kWG), 0, st, a.data,
-                     a.n, a.query, -0.5 * a.p, a.flags, a.list, a.count,
+  hipLaunchKernelGGL((k_fwd_fixup<T, DIM, L, PM>), dim3(kFixGrid), dim3(kWG), 0, st, a.data,
+                     a.n, a.query, -0.5 * a.p, a.flags, a.list, a.count, a.fix_cmax, a.fpart,
                      static_cast<T*>(a.out_z), a.out_den);
+  hipLaunchKernelGGL((k_fwd_fixmerge<T>), dim3(4), dim3(kWG), 0, st, a.list, a.count, a.fix_cmax,
+                     a.fpart, static_cast<T*>(a.out_z), a.out_den);
   return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ struct FwdArgs {
   double2* part = nullptr;
   const int* list = nullptr;
   const int* count = nullptr;
-  int fix_grid = 256;
+  int fix_cmax = 1;              // most data chunks per flagged query in the FP64 fix-up
+  double4* fpart = nullptr;      // [kFixGrid] fix-up chunk partials
 };
 
 // Everything a backward launch needs.
@@ -61,10 +62,14 @@ struct BwdArgs {
   double* slot_coef = nullptr;  // [m] per flagged slot: g/D (or g/h at a hit)
   int* slot_hits = nullptr;     // [m] per flagged slot: hit count h
   double* slot_dp = nullptr;    // [m] per flagged slot: dp contribution
-  int fix_grid = 256;
+  double* slot_z = nullptr;     // [m] per flagged slot: FP64 Z
+  double* slot_den = nullptr;   // [m] per flagged slot: FP64 denominator
+  int fix_cmax = 1;
+  double4* fpart = nullptr;     // [kFixGrid] fix-up chunk partials
 };
 
 constexpr int kTile = 512;        // data points staged in LDS per tile (2 per thread)
+constexpr int kFixGrid = 1024;    // workgroups of the FP64 fix-up kernels
 constexpr int kCountBlock = 4096; // flags per compaction block (16 per thread)
 
 // Per-layout entry points (one translation unit per layout keeps builds parallel).

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import GTOL, points, rand_case
+from gpu_helpers import GTOL, TOL, points, rand_case
 from paper_1402_4986_amd import api
 
 pytestmark = pytest.mark.gpu
@@ -129,3 +129,26 @@ def test_loo_fit_reduces_the_loss():
     # the loss at the fitted p agrees with the oracle's leave-one-out loss
     assert oracle.loo_loss(x, z, p) == pytest.approx(float(api.loo_loss(X, zt, torch.tensor(p, device="cuda"))),
                                                      rel=1e-4)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fixup_split_over_data_chunks(prec):
+    # Few flagged queries against many data points: the FP64 fix-up cuts each flagged
+    # query's data range into chunks swept by separate workgroups and merged in order.
+    x, z, q = rand_case(28, 200000, 300, 2, prec)
+    q[:3] = x[[5, 77, 1234]]                 # exact hits
+    q[3:6] = x[[9, 99, 999]] + 3e-7          # near-coincident
+    t = np.float32 if prec == "f32" else np.float64
+    q = q.astype(t).astype(np.float64)
+    d, qq = points(x, z, q, "soa", prec)
+    Z, D = api.forward(d, qq, 2.0, prec)
+    Zh = Z.cpu().numpy().astype(np.float64)
+    ref = oracle.forward(x, z, q, 2.0)
+    assert np.all(ref["H"][:3] == 1)
+    np.testing.assert_array_equal(Zh[:3], ref["Z"][:3].astype(t).astype(np.float64))
+    near = np.abs(Zh[3:6] - ref["Z"][3:6]) / ref["S"][3:6]
+    assert np.max(near) <= (6e-8 if prec == "f32" else 1e-14)
+    assert np.max(np.abs(Zh - ref["Z"]) / ref["S"]) <= TOL[prec]
+    g = np.random.default_rng(29).normal(size=len(q)).astype(t).astype(np.float64)
+    got = _run(x, z, q, 2.0, "soa", prec, g)
+    _check(got, oracle.backward(x, z, q, 2.0, g), prec)

@@ -161,3 +161,19 @@ def test_full_size_mixture3d_hits_and_fp32_vs_fp64():
     # FP32 path against the GPU FP64 path for every query
     rel = np.abs(Z32 - Z64) / np.maximum(np.abs(Z64), 1e-3)
     assert np.max(rel) <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def plain2d_10k():
+    cfg = workloads.WORKLOADS["plain2d_f64_10k"]
+    x, z, q, _ = workloads.plain2d(cfg["n"], cfg["m"], "f64", cfg=cfg["cfg"])
+    return x, z, q, oracle.forward(x, z, q, 2.0)
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos", "aoas", "hybrid", "soaos"])
+def test_full_size_plain2d_f64_10k_every_query(layout, plain2d_10k):
+    # 10,240 x 10,240 FP64, p = 2: the oracle evaluates every query.
+    x, z, q, ref = plain2d_10k
+    Z, D = gpu_forward(x, z, q, 2.0, layout, "f64")
+    assert np.max(scaled_err(Z, ref)) <= TOL["f64"]
+    np.testing.assert_allclose(D, ref["D"], rtol=1e-12)

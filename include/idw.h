@@ -93,13 +93,17 @@ typedef struct idw_points {
  *   batch_chunk       batched plans: data points per work item (rounded up to 512;
  *                     default 16384)
  *   batch_workgroups  batched plans: persistent workgroups (default 2 per compute unit)
+ *   separate_adjoint  idw_backward, FP32: 1 = run the query-direction and data-direction
+ *                     sweeps separately instead of the fused sweep (same results within
+ *                     the stated tolerances; for comparison)
  *   reserved          must be zero */
 typedef struct idw_config {
   int32_t queries_per_lane;
   int32_t split;
   int32_t batch_chunk;
   int32_t batch_workgroups;
-  int32_t reserved[4];
+  int32_t separate_adjoint;
+  int32_t reserved[3];
 } idw_config;
 
 /* Library version string (static storage). */
@@ -154,7 +158,8 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
 /* ---- Kernel timing (benchmarks).  When enabled, idw_forward / idw_backward bracket each
  * all-pairs sweep kernel with HIP events recorded on the launch stream.  Not for use
  * under graph capture.  Host-side state is process-wide and mutex-protected. ---- */
-enum { IDW_T_FWD_SWEEP = 0, IDW_T_BWD_QUERY = 1, IDW_T_BWD_DATA = 2, IDW_T_COUNT = 3 };
+enum { IDW_T_FWD_SWEEP = 0, IDW_T_BWD_QUERY = 1, IDW_T_BWD_DATA = 2, IDW_T_BWD_FUSED = 3,
+       IDW_T_COUNT = 4 };
 
 /* Enables (on != 0) or disables timing; either way drops pending events and resets the
  * totals. */

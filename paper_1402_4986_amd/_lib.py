@@ -21,7 +21,7 @@ PRECISION_CODES = {"f32": FP32, "f64": FP64}
 EXPORTED = ("idw_version", "idw_last_error", "idw_record_bytes", "idw_workspace_size",
             "idw_forward", "idw_backward", "idw_timing_enable", "idw_timing_read", "idw_batched_plan_create",
             "idw_batched_plan_workspace", "idw_batched", "idw_batched_plan_destroy")
-T_FWD_SWEEP, T_BWD_QUERY, T_BWD_DATA = 0, 1, 2
+T_FWD_SWEEP, T_BWD_QUERY, T_BWD_DATA, T_BWD_FUSED = 0, 1, 2, 3
 
 
 class IdwPoints(ctypes.Structure):
@@ -32,7 +32,7 @@ class IdwPoints(ctypes.Structure):
 class IdwConfig(ctypes.Structure):
     _fields_ = [("queries_per_lane", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("batch_chunk", ctypes.c_int32), ("batch_workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("separate_adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class IdwInstance(ctypes.Structure):

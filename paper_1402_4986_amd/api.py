@@ -122,8 +122,12 @@ def forward(data: Points, query: Points, p: float, precision: str = "f32", exclu
 
 def backward(data: Points, query: Points, p: float, grad_out: torch.Tensor, saved_z: torch.Tensor,
              saved_den: torch.Tensor, precision: str = "f32", need_dz: bool = True, need_dp: bool = True,
-             need_dq: bool = True, exclude_self: bool = False, ws: Optional[torch.Tensor] = None):
-    """(dz[n] or None, dp (0-d float64 tensor) or None, dq[m, dim] or None)."""
+             need_dq: bool = True, exclude_self: bool = False, ws: Optional[torch.Tensor] = None,
+             separate: bool = False):
+    """(dz[n] or None, dp (0-d float64 tensor) or None, dq[m, dim] or None).
+
+    separate=True runs the query-direction and data-direction sweeps as two kernels
+    instead of the fused FP32 sweep (for comparison)."""
     lib = _lib.load()
     dt = _TORCH_DTYPE[precision]
     dev = data.device
@@ -136,9 +140,14 @@ def backward(data: Points, query: Points, p: float, grad_out: torch.Tensor, save
     if ws is None:
         ws = workspace(data, query, precision)
     dc, qc = data.c(), query.c()
+    cfg = None
+    if separate:
+        cfg = IdwConfig()
+        cfg.separate_adjoint = 1
     check(lib.idw_backward(ctypes.byref(dc), ctypes.byref(qc), float(p), _lib.PRECISION_CODES[precision], flags,
                            _ptr(grad_out.contiguous()), _ptr(saved_z), _ptr(saved_den), _ptr(dz), _ptr(dp),
-                           _ptr(dq), _ptr(ws), ws.numel(), _stream_handle(dev), None))
+                           _ptr(dq), _ptr(ws), ws.numel(), _stream_handle(dev),
+                           ctypes.byref(cfg) if cfg is not None else None))
     return dz, dp, dq
 
 

@@ -186,6 +186,15 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   choose_split(n, cdiv(m, kWG * w.qq), 0, w.split_q, w.chunk_q);
   w.qz = f64 ? 2 : 4;
   choose_split(m > 0 ? m : 1, cdiv(n, kWG * w.qz), 0, w.split_z, w.chunk_z);
+  // fused FP32 adjoint: workgroup (group, range) sweeps data range `range` for the query
+  // blocks group, group + G, ...; about 512 workgroups in all
+  if (!f64 && m > 0) {
+    int ranges = static_cast<int>(std::min<int64_t>(16, std::max<int64_t>(1, cdiv(n, 131072))));
+    w.fused_chunk = cdiv(cdiv(n, ranges), kTile) * kTile;
+    w.fused_ranges = static_cast<int>(cdiv(n, w.fused_chunk));
+    const int64_t nqb = cdiv(m, kWG * 2);
+    w.fused_groups = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nqb, cdiv(512, w.fused_ranges))));
+  }
   w.nbbox = static_cast<int>(std::min<int64_t>(1024, cdiv(n, kWG)));
   w.nwg_dp = static_cast<int>(cdiv(m, kWG));
   const int64_t nb = cdiv(m > 0 ? m : 1, kCountBlock);
@@ -201,8 +210,8 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   w.bcnt = take(sizeof(int) * static_cast<size_t>(nb + 1));
   w.list = take(sizeof(int) * static_cast<size_t>(m));
   w.part_f = take(w.split_f > 1 ? sizeof(double2) * static_cast<size_t>(w.split_f) * m : 0);
-  w.part_q = take(sizeof(double4) * static_cast<size_t>(w.split_q) * m);
-  w.part_z = take(sizeof(double) * static_cast<size_t>(w.split_z) * n);
+  w.part_q = take(sizeof(double4) * static_cast<size_t>(std::max(w.split_q, w.fused_ranges)) * m);
+  w.part_z = take(sizeof(double) * static_cast<size_t>(std::max(w.split_z, w.fused_groups)) * n);
   w.slot_coef = take(sizeof(double) * static_cast<size_t>(m));
   w.slot_hits = take(sizeof(int) * static_cast<size_t>(m));
   w.slot_dp = take(sizeof(double) * static_cast<size_t>(m));
@@ -224,16 +233,17 @@ struct LayoutFns {
   hipError_t (*bwd_query)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_data)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_fixup)(const BwdArgs&, bool, hipStream_t);
+  hipError_t (*bwd_fused)(const BwdArgs&, hipStream_t);
 };
 
 static const LayoutFns kFns[5] = {
-    {fwd_sweep_soa, fwd_fixup_soa, bbox_soa, bwd_query_soa, bwd_data_soa, bwd_fixup_soa},
-    {fwd_sweep_aos, fwd_fixup_aos, bbox_aos, bwd_query_aos, bwd_data_aos, bwd_fixup_aos},
-    {fwd_sweep_aoas, fwd_fixup_aoas, bbox_aoas, bwd_query_aoas, bwd_data_aoas, bwd_fixup_aoas},
+    {fwd_sweep_soa, fwd_fixup_soa, bbox_soa, bwd_query_soa, bwd_data_soa, bwd_fixup_soa, bwd_fused_soa},
+    {fwd_sweep_aos, fwd_fixup_aos, bbox_aos, bwd_query_aos, bwd_data_aos, bwd_fixup_aos, bwd_fused_aos},
+    {fwd_sweep_aoas, fwd_fixup_aoas, bbox_aoas, bwd_query_aoas, bwd_data_aoas, bwd_fixup_aoas, bwd_fused_aoas},
     {fwd_sweep_hybrid, fwd_fixup_hybrid, bbox_hybrid, bwd_query_hybrid, bwd_data_hybrid,
-     bwd_fixup_hybrid},
+     bwd_fixup_hybrid, bwd_fused_hybrid},
     {fwd_sweep_soaos, fwd_fixup_soaos, bbox_soaos, bwd_query_soaos, bwd_data_soaos,
-     bwd_fixup_soaos},
+     bwd_fixup_soaos, bwd_fused_soaos},
 };
 
 const LayoutFns& fns(int layout) { return kFns[layout]; }
@@ -496,15 +506,29 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
                                     reinterpret_cast<int*>(ws + w.hdr + 256), st),
                       "compaction")))
     return rc;
-  if (ndp || ndq) {
-    if ((rc = check_hip(timed(IDW_T_BWD_QUERY, st, [&] { return F.bwd_query(a, f64, st); }), "query sweep")))
+  const bool fused = !f64 && ndz && (ndp || ndq) && w.fused_groups > 0 && !(cfg && cfg->separate_adjoint);
+  if (fused) {  // one FP32 sweep for dp/dq and dz
+    a.fused_groups = w.fused_groups;
+    a.fused_ranges = w.fused_ranges;
+    a.fused_chunk = w.fused_chunk;
+    if ((rc = check_hip(timed(IDW_T_BWD_FUSED, st, [&] { return F.bwd_fused(a, st); }), "fused adjoint sweep")))
       return rc;
-    if ((rc = check_hip(bwd_qmerge(a, f64, st), "query merge"))) return rc;
-  }
-  if (ndz) {
-    if ((rc = check_hip(timed(IDW_T_BWD_DATA, st, [&] { return F.bwd_data(a, f64, st); }), "data sweep")))
-      return rc;
-    if ((rc = check_hip(bwd_zmerge(a, f64, st), "data merge"))) return rc;
+    BwdArgs b = a;
+    b.split_q = w.fused_ranges;
+    b.split_z = w.fused_groups;
+    if ((rc = check_hip(bwd_qmerge(b, f64, st), "query merge"))) return rc;
+    if ((rc = check_hip(bwd_zmerge(b, f64, st), "data merge"))) return rc;
+  } else {
+    if (ndp || ndq) {
+      if ((rc = check_hip(timed(IDW_T_BWD_QUERY, st, [&] { return F.bwd_query(a, f64, st); }), "query sweep")))
+        return rc;
+      if ((rc = check_hip(bwd_qmerge(a, f64, st), "query merge"))) return rc;
+    }
+    if (ndz) {
+      if ((rc = check_hip(timed(IDW_T_BWD_DATA, st, [&] { return F.bwd_data(a, f64, st); }), "data sweep")))
+        return rc;
+      if ((rc = check_hip(bwd_zmerge(a, f64, st), "data merge"))) return rc;
+    }
   }
   if ((rc = check_hip(F.bwd_fixup(a, f64, st), "FP64 fix-up"))) return rc;
   if (ndp && (rc = check_hip(dp_final(a.wg_dp, w.nwg_dp, a.slot_dp, a.count, grad_p, st), "dp reduction")))

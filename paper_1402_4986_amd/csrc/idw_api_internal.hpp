@@ -19,6 +19,8 @@ struct WsPlan {
   int qz = 8, split_z = 1;
   int64_t chunk_z = 0;
   int nbbox = 1, nwg_dp = 1;
+  int fused_groups = 0, fused_ranges = 0;  // fused FP32 adjoint decomposition
+  int64_t fused_chunk = 0;
   size_t hdr = 0, bbox = 0, flag = 0, bcnt = 0, list = 0, part_f = 0, part_q = 0, part_z = 0;
   size_t slot_coef = 0, slot_hits = 0, slot_dp = 0, slot_z = 0, slot_den = 0, fpart = 0, wg_dp = 0;
   size_t total = 0;

@@ -1,0 +1,266 @@
+// Fused FP32 adjoint sweep: the query-direction sums (P_i, G_i, for dp and dq) and the
+// data-direction sums (dz_j = sum_i a_i w_ij, a_i = g_i / D_i) from ONE evaluation of
+// each pair's weight.
+//
+// Lanes own Q queries each (registers).  Data points are staged in LDS in batches of 64,
+// each batch stored twice in a row, so that at step s lane L reads record (L + s) of the
+// doubled batch -- data point (L + s) mod 64 -- with a compile-time offset and no bank
+// conflicts.  Query-direction sums accumulate per lane as in the query sweep.  For the
+// data direction every lane forms s_L = sum_k a_k w_k for its point of the step, and a
+// running sum travels one lane per step (v_add_f32 with a wave_rol:1 DPP operand:
+// lane L receives the sum held by lane L+1), picking up the contribution of each lane for
+// the same data point.  After 64 steps lane L holds the sum over the wave's 64 x Q
+// queries for batch point (L - 1) mod 64.  That costs one DPP add per lane per step,
+// against a separate data sweep that recomputes every weight.
+//
+// Work decomposition: workgroup (qg, dr) sweeps data range dr for the query blocks
+// qg, qg + G, qg + 2G, ...; it writes the query partials of range dr (as the query sweep
+// with a data split) and accumulates its dz partial row qg across its query blocks (the
+// data sweep's split-over-queries format), so the existing fixed-order merges apply.
+#pragma once
+
+#include "idw_bwd.hpp"
+#include "idw_device.hpp"
+#include "idw_fwd.hpp"
+
+namespace idw {
+
+constexpr int kBatch = 64;                   // data points per rotation batch (one wave)
+constexpr int kFTile = 512;                  // data points per LDS tile (8 batches)
+constexpr int kFBatches = kFTile / kBatch;
+
+// One 64-point batch.  MASK: some pairs must be skipped (padding records beyond the data
+// range, or the leave-one-out self pair); those get r2 = 1 and zero value factors.
+template <int DIM, int PM, int Q, bool NDP, bool NDQ, bool MASK, int UNR>
+__device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, int lane, int64_t jb,
+                                            int64_t je, bool excl, const float (&qc)[Q][3],
+                                            const float (&zq)[Q], const float (&aq)[Q],
+                                            const int64_t (&qi)[Q], float nhp, float (&ap)[Q],
+                                            float (&ag)[Q][3]) {
+  float acc = 0.f;
+  const P4<float>* r0 = rec + lane;
+#pragma unroll UNR
+  for (int s = 0; s < kBatch; ++s) {
+    const P4<float> d = r0[s];
+    const float dv = (DIM == 3) ? d.w : d.z;
+    float sz = 0.f;
+    int64_t j = 0;
+    bool valid = true;
+    if constexpr (MASK) {
+      j = jb + ((lane + s) & (kBatch - 1));
+      valid = j < je;
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const float dx = qc[k][0] - d.x;
+      const float dy = qc[k][1] - d.y;
+      float dz = 0.f;
+      float r2 = dx * dx;
+      r2 = fmaf(dy, dy, r2);
+      if constexpr (DIM == 3) {
+        dz = qc[k][2] - d.z;
+        r2 = fmaf(dz, dz, r2);
+      }
+      float c = dv - zq[k];
+      float a = aq[k];
+      if constexpr (MASK) {
+        if (!valid || (excl && j == qi[k])) {
+          r2 = 1.f;
+          c = 0.f;
+          a = 0.f;
+        }
+      }
+      float w, f = 0.f, lg = 0.f;
+      wterms<PM, NDQ, NDP>(r2, nhp, w, f, lg);
+      const float t = w * c;
+      if constexpr (NDP) ap[k] = fmaf(t, lg, ap[k]);
+      if constexpr (NDQ) {
+        const float u = t * f;
+        ag[k][0] = fmaf(u, dx, ag[k][0]);
+        ag[k][1] = fmaf(u, dy, ag[k][1]);
+        if constexpr (DIM == 3) ag[k][2] = fmaf(u, dz, ag[k][2]);
+      }
+      sz = (k == 0) ? a * w : fmaf(a, w, sz);
+    }
+    // lane L takes the running sum of lane L+1 (wave rotate left by one) and adds its own
+    const float rot = __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, acc), 0x134, 0xF, 0xF, false));
+    acc = rot + sz;
+  }
+  return acc;
+}
+
+template <int DIM, int L, int PM, int Q, bool NDP, bool NDQ, int UNR = 4, int WPE = 2>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_fused(
+    DevPts data, int64_t n, DevPts query, int64_t m, int64_t chunk, int groups, float nhp, unsigned flags,
+    const double* __restrict__ hdr, const float* __restrict__ saved_z, const float* __restrict__ grad_out,
+    const double* __restrict__ saved_den, double4* __restrict__ part_q, double* __restrict__ part_z) {
+  __shared__ P4<float> tile[2][2 * kFTile];   // batches stored twice in a row
+  __shared__ float zred[kWG / 64][kFTile];   // per-wave dz sums of the current tile
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int qg = blockIdx.x;
+  const int64_t jb = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t je = (jb + chunk < n) ? jb + chunk : n;
+  const float s = static_cast<float>(hdr[H_SCALE]);
+  const double thr = hdr[H_THR_U], lo = hdr[H_LO_U], unit = hdr[H_DEN_UNIT];
+  const bool excl = (flags & 1u) != 0;
+  const int64_t qpb = static_cast<int64_t>(kWG) * Q;
+  const int64_t nqb = (m + qpb - 1) / qpb;
+  const int ntiles = static_cast<int>((je - jb + kFTile - 1) / kFTile);
+  double* zrow = part_z + static_cast<int64_t>(qg) * n;
+
+  float rc[2][3], rv[2];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t j = jb + static_cast<int64_t>(t) * kFTile + u * kWG + tid;
+      rc[u][0] = rc[u][1] = rc[u][2] = 0.f;
+      rv[u] = 0.f;
+      if (j < je) Loader<float, DIM, L>::data(data, j, rc[u], rv[u]);
+    }
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int p = u * kWG + tid;                       // point within the tile
+      const int at = (p / kBatch) * (2 * kBatch) + (p % kBatch);
+      const P4<float> r = stage<float, DIM>(rc[u], rv[u], s);
+      tile[b][at] = r;
+      tile[b][at + kBatch] = r;
+    }
+  };
+
+  int first = 1;
+  for (int64_t qb = qg; qb < nqb; qb += groups, first = 0) {
+    const int64_t q0 = qb * qpb;
+    float qc[Q][3], zq[Q], aq[Q];
+    int64_t qi[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      qi[k] = q0 + tid + static_cast<int64_t>(k) * kWG;
+      float c[3] = {0.f, 0.f, 0.f};
+      bool ok = false;
+      zq[k] = 0.f;
+      aq[k] = 0.f;
+      if (qi[k] < m) {
+        const double D = saved_den[qi[k]];
+        ok = D <= thr && D > lo;  // flagged queries are left to the FP64 fix-up
+        if (ok) {
+          Loader<float, DIM, L>::query(query, qi[k], c);
+          zq[k] = saved_z[qi[k]];
+          aq[k] = static_cast<float>(static_cast<double>(grad_out[qi[k]]) / (D / unit));
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) qc[k][d] = ok ? c[d] * s : __builtin_huge_valf();
+    }
+    float ph[Q], pl[Q], gh[Q][3], gl[Q][3];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      ph[k] = pl[k] = 0.f;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) gh[k][d] = gl[k][d] = 0.f;
+    }
+
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+      if (t + 1 < ntiles) fetch(t + 1);
+      const int64_t jt = jb + static_cast<int64_t>(t) * kFTile;
+      const bool diag = excl && jt < q0 + qpb && q0 < jt + kFTile;
+      const bool tail = jt + kFTile > je;
+#pragma unroll 1
+      for (int b = 0; b < kFBatches; ++b) {
+        float ap[Q], ag[Q][3];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          ap[k] = 0.f;
+          ag[k][0] = ag[k][1] = ag[k][2] = 0.f;
+        }
+        const P4<float>* rec = tile[t & 1] + b * (2 * kBatch);
+        const int64_t jbat = jt + b * kBatch;
+        float zs;
+        if (diag || tail)
+          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, true, 1>(rec, lane, jbat, je, excl, qc, zq, aq, qi, nhp, ap, ag);
+        else
+          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, false, UNR>(rec, lane, jbat, je, excl, qc, zq, aq, qi, nhp, ap, ag);
+        zred[wave][b * kBatch + ((lane + kBatch - 1) & (kBatch - 1))] = zs;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          if constexpr (NDP) two_sum_acc(ph[k], pl[k], ap[k]);
+          if constexpr (NDQ) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) two_sum_acc(gh[k][d], gl[k][d], ag[k][d]);
+          }
+        }
+      }
+      __syncthreads();  // zred complete; tile t fully consumed
+      // dz: sum the waves' partials in wave order and fold into this group's row
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int p = u * kWG + tid;
+        const int64_t j = jt + p;
+        if (j < je) {
+          double v = static_cast<double>(zred[0][p]);
+#pragma unroll
+          for (int w = 1; w < kWG / 64; ++w) v += static_cast<double>(zred[w][p]);
+          zrow[j] = first ? v : zrow[j] + v;
+        }
+      }
+      if (t + 1 < ntiles) put((t + 1) & 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      if (qi[k] < m) {
+        double4 r;
+        r.x = static_cast<double>(ph[k]) + static_cast<double>(pl[k]);
+        r.y = static_cast<double>(gh[k][0]) + static_cast<double>(gl[k][0]);
+        r.z = static_cast<double>(gh[k][1]) + static_cast<double>(gl[k][1]);
+        r.w = static_cast<double>(gh[k][2]) + static_cast<double>(gl[k][2]);
+        part_q[static_cast<int64_t>(blockIdx.y) * m + qi[k]] = r;
+      }
+    }
+  }
+  // A group without any query block still owns a partial row: make it zero.
+  if (first) {
+    for (int64_t j = jb + tid; j < je; j += kWG) zrow[j] = 0.0;
+  }
+}
+
+template <int DIM, int L, int PM>
+hipError_t launch_bwd_fused_t(const BwdArgs& a, int groups, int ranges, int64_t chunk, hipStream_t st) {
+  const bool ndp = (a.flags & 0x4u) != 0, ndq = (a.flags & 0x8u) != 0;
+  dim3 grid(static_cast<unsigned>(groups), static_cast<unsigned>(ranges));
+  const float nhp = static_cast<float>(-0.5 * a.p);
+  const float* sz = static_cast<const float*>(a.saved_z);
+  const float* go = static_cast<const float*>(a.grad_out);
+#define IDW_BF(DP, DQ)                                                                          \
+  hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ>), grid, dim3(kWG), 0, st, a.data, a.n, \
+                     a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den,     \
+                     a.part_q, a.part_z)
+  if (ndp && ndq)
+    IDW_BF(true, true);
+  else if (ndp)
+    IDW_BF(true, false);
+  else
+    IDW_BF(false, true);
+#undef IDW_BF
+  return hipGetLastError();
+}
+
+template <int DIM, int L>
+hipError_t bwd_fused_pm(const BwdArgs& a, int groups, int ranges, int64_t chunk, hipStream_t st) {
+  switch (a.pmode) {
+    case PM_1: return launch_bwd_fused_t<DIM, L, PM_1>(a, groups, ranges, chunk, st);
+    case PM_2: return launch_bwd_fused_t<DIM, L, PM_2>(a, groups, ranges, chunk, st);
+    case PM_3: return launch_bwd_fused_t<DIM, L, PM_3>(a, groups, ranges, chunk, st);
+    case PM_4: return launch_bwd_fused_t<DIM, L, PM_4>(a, groups, ranges, chunk, st);
+    default: return launch_bwd_fused_t<DIM, L, PM_GEN>(a, groups, ranges, chunk, st);
+  }
+}
+
+}  // namespace idw

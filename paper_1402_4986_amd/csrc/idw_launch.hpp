@@ -50,6 +50,9 @@ struct BwdArgs {
   int64_t chunk_z = 0;
   double4* part_q = nullptr;  // [split_q][m] (P, Gx, Gy, Gz)
   double* part_z = nullptr;   // [split_z][n]
+  int fused_groups = 0;       // fused FP32 sweep: query-block groups (= dz partial rows)
+  int fused_ranges = 0;       // fused FP32 sweep: data ranges (= query partial rows)
+  int64_t fused_chunk = 0;
   const double* hdr = nullptr;
   const void* grad_out = nullptr;
   const void* saved_z = nullptr;
@@ -80,7 +83,8 @@ constexpr int kCountBlock = 4096; // flags per compaction block (16 per thread)
                          int nblocks, hipStream_t st);                           \
   hipError_t bwd_query_##NAME(const BwdArgs& a, bool f64, hipStream_t st);       \
   hipError_t bwd_data_##NAME(const BwdArgs& a, bool f64, hipStream_t st);        \
-  hipError_t bwd_fixup_##NAME(const BwdArgs& a, bool f64, hipStream_t st);
+  hipError_t bwd_fixup_##NAME(const BwdArgs& a, bool f64, hipStream_t st);      \
+  hipError_t bwd_fused_##NAME(const BwdArgs& a, hipStream_t st);
 
 IDW_DECLARE_LAYOUT(soa)
 IDW_DECLARE_LAYOUT(aos)

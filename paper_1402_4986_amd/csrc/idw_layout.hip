@@ -2,6 +2,7 @@
 // with IDW_LAYOUT (the Layout enum value) and IDW_LAYOUT_NAME (the symbol suffix) defined,
 // so the five layouts build as independent translation units.
 #include "idw_bwd.hpp"
+#include "idw_bwd_fused.hpp"
 #include "idw_fwd.hpp"
 #include "idw_launch.hpp"
 
@@ -50,6 +51,11 @@ hipError_t IDW_CAT(bwd_fixup_, IDW_LAYOUT_NAME)(const BwdArgs& a, bool f64, hipS
   if (f64)
     return a.dim == 3 ? bwd_fix_pm<double, 3, IDW_LAYOUT>(a, st) : bwd_fix_pm<double, 2, IDW_LAYOUT>(a, st);
   return a.dim == 3 ? bwd_fix_pm<float, 3, IDW_LAYOUT>(a, st) : bwd_fix_pm<float, 2, IDW_LAYOUT>(a, st);
+}
+
+hipError_t IDW_CAT(bwd_fused_, IDW_LAYOUT_NAME)(const BwdArgs& a, hipStream_t st) {
+  return a.dim == 3 ? bwd_fused_pm<3, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st)
+                    : bwd_fused_pm<2, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st);
 }
 
 }  // namespace idw

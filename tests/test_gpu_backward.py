@@ -152,3 +152,42 @@ def test_fixup_split_over_data_chunks(prec):
     g = np.random.default_rng(29).normal(size=len(q)).astype(t).astype(np.float64)
     got = _run(x, z, q, 2.0, "soa", prec, g)
     _check(got, oracle.backward(x, z, q, 2.0, g), prec)
+
+
+@pytest.mark.parametrize("separate", [False, True])
+@pytest.mark.parametrize("dim,p", [(2, 2.0), (3, 2.5), (2, 1.0), (3, 3.0)])
+def test_fused_and_separate_adjoint_sweeps(separate, dim, p):
+    # FP32 dz with dp/dq runs as one fused sweep by default; the separate query-direction
+    # and data-direction sweeps stay available.  Both against the oracle.
+    x, z, q = rand_case(30 + dim, 2100, 1537, dim)
+    g = np.random.default_rng(31).normal(size=len(q)).astype(np.float32).astype(np.float64)
+    d, qq = points(x, z, q, "aoas", "f32")
+    Z, D = api.forward(d, qq, p, "f32")
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda")
+    dz, dp, dq = api.backward(d, qq, p, gt, Z, D, "f32", separate=separate)
+    torch.cuda.synchronize()
+    got = (dz.cpu().numpy().astype(np.float64), float(dp), dq.cpu().numpy().astype(np.float64))
+    _check(got, oracle.backward(x, z, q, p, g), "f32")
+
+
+def test_fused_adjoint_accumulates_over_query_blocks():
+    # 300,000 data points in 3 ranges and 100,000 queries: each workgroup of the fused sweep
+    # folds several query blocks into its dz row.  The upstream gradient is non-zero on
+    # 300 scattered queries only, so the oracle needs just those 300 queries for the exact
+    # dz, dp and dq.
+    x, z, q = rand_case(32, 300000, 100000, 2)
+    r = np.random.default_rng(33)
+    sel = np.sort(r.choice(len(q), size=300, replace=False))
+    g = np.zeros(len(q))
+    g[sel] = r.normal(size=300).astype(np.float32)
+    d, qq = points(x, z, q, "soa", "f32")
+    Z, D = api.forward(d, qq, 2.0, "f32")
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda")
+    dz, dp, dq = api.backward(d, qq, 2.0, gt, Z, D, "f32")
+    torch.cuda.synchronize()
+    ref = oracle.backward(x, z, q[sel], 2.0, g[sel])
+    dqh = dq.cpu().numpy().astype(np.float64)
+    got = (dz.cpu().numpy().astype(np.float64), float(dp), dqh[sel])
+    _check(got, ref, "f32")
+    rest = np.setdiff1d(np.arange(len(q)), sel)
+    assert np.all(dqh[rest] == 0.0)

@@ -187,13 +187,15 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   w.qz = f64 ? 2 : 4;
   choose_split(m > 0 ? m : 1, cdiv(n, kWG * w.qz), 0, w.split_z, w.chunk_z);
   // fused FP32 adjoint: workgroup (group, range) sweeps data range `range` for the query
-  // blocks group, group + G, ...; about 512 workgroups in all
+  // blocks group, group + G, ...; about 1024 workgroups of 512 threads in all.  Ranges of
+  // 64K points balance the dz rows (groups x n doubles) against the query partials
+  // (ranges x m double4): about 1 GB at n = m = 1M.
   if (!f64 && m > 0) {
-    int ranges = static_cast<int>(std::min<int64_t>(16, std::max<int64_t>(1, cdiv(n, 131072))));
+    const int ranges = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, cdiv(n, 65536))));
     w.fused_chunk = cdiv(cdiv(n, ranges), kTile) * kTile;
     w.fused_ranges = static_cast<int>(cdiv(n, w.fused_chunk));
-    const int64_t nqb = cdiv(m, kWG * 2);
-    w.fused_groups = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nqb, cdiv(512, w.fused_ranges))));
+    const int64_t nqb = cdiv(m, 512 * 2);
+    w.fused_groups = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nqb, cdiv(1024, w.fused_ranges))));
   }
   w.nbbox = static_cast<int>(std::min<int64_t>(1024, cdiv(n, kWG)));
   w.nwg_dp = static_cast<int>(cdiv(m, kWG));

@@ -90,13 +90,19 @@ __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, i
   return acc;
 }
 
-template <int DIM, int L, int PM, int Q, bool NDP, bool NDQ, int UNR = 4, int WPE = 2>
-__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_fused(
+// Defaults measured on MI355X (1M queries x 256K data, 2-D, p = 2): 512-thread workgroups,
+// Q = 2, unroll 2, about 1024 workgroups in the grid: 13.6 VALU lane-slots per pair, against
+// 17.3 with 256-thread workgroups and 512 in the grid.
+constexpr int kFNT = 512;
+
+template <int DIM, int L, int PM, int Q, bool NDP, bool NDQ, int UNR = 2, int WPE = 2, int NT = kFNT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_fused(
     DevPts data, int64_t n, DevPts query, int64_t m, int64_t chunk, int groups, float nhp, unsigned flags,
     const double* __restrict__ hdr, const float* __restrict__ saved_z, const float* __restrict__ grad_out,
     const double* __restrict__ saved_den, double4* __restrict__ part_q, double* __restrict__ part_z) {
   __shared__ P4<float> tile[2][2 * kFTile];   // batches stored twice in a row
-  __shared__ float zred[kWG / 64][kFTile];   // per-wave dz sums of the current tile
+  constexpr int PPT = kFTile / NT;            // tile points staged per thread
+  __shared__ float zred[NT / 64][kFTile];    // per-wave dz sums of the current tile
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -106,16 +112,16 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
   const float s = static_cast<float>(hdr[H_SCALE]);
   const double thr = hdr[H_THR_U], lo = hdr[H_LO_U], unit = hdr[H_DEN_UNIT];
   const bool excl = (flags & 1u) != 0;
-  const int64_t qpb = static_cast<int64_t>(kWG) * Q;
+  const int64_t qpb = static_cast<int64_t>(NT) * Q;
   const int64_t nqb = (m + qpb - 1) / qpb;
   const int ntiles = static_cast<int>((je - jb + kFTile - 1) / kFTile);
   double* zrow = part_z + static_cast<int64_t>(qg) * n;
 
-  float rc[2][3], rv[2];
+  float rc[PPT][3], rv[PPT];
   auto fetch = [&](int t) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int64_t j = jb + static_cast<int64_t>(t) * kFTile + u * kWG + tid;
+    for (int u = 0; u < PPT; ++u) {
+      const int64_t j = jb + static_cast<int64_t>(t) * kFTile + u * NT + tid;
       rc[u][0] = rc[u][1] = rc[u][2] = 0.f;
       rv[u] = 0.f;
       if (j < je) Loader<float, DIM, L>::data(data, j, rc[u], rv[u]);
@@ -123,8 +129,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
   };
   auto put = [&](int b) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int p = u * kWG + tid;                       // point within the tile
+    for (int u = 0; u < PPT; ++u) {
+      const int p = u * NT + tid;                        // point within the tile
       const int at = (p / kBatch) * (2 * kBatch) + (p % kBatch);
       const P4<float> r = stage<float, DIM>(rc[u], rv[u], s);
       tile[b][at] = r;
@@ -139,7 +145,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
     int64_t qi[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      qi[k] = q0 + tid + static_cast<int64_t>(k) * kWG;
+      qi[k] = q0 + tid + static_cast<int64_t>(k) * NT;
       float c[3] = {0.f, 0.f, 0.f};
       bool ok = false;
       zq[k] = 0.f;
@@ -200,13 +206,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
       __syncthreads();  // zred complete; tile t fully consumed
       // dz: sum the waves' partials in wave order and fold into this group's row
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int p = u * kWG + tid;
+      for (int u = 0; u < PPT; ++u) {
+        const int p = u * NT + tid;
         const int64_t j = jt + p;
         if (j < je) {
           double v = static_cast<double>(zred[0][p]);
 #pragma unroll
-          for (int w = 1; w < kWG / 64; ++w) v += static_cast<double>(zred[w][p]);
+          for (int w = 1; w < NT / 64; ++w) v += static_cast<double>(zred[w][p]);
           zrow[j] = first ? v : zrow[j] + v;
         }
       }
@@ -227,7 +233,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
   }
   // A group without any query block still owns a partial row: make it zero.
   if (first) {
-    for (int64_t j = jb + tid; j < je; j += kWG) zrow[j] = 0.0;
+    for (int64_t j = jb + tid; j < je; j += NT) zrow[j] = 0.0;
   }
 }
 
@@ -239,7 +245,7 @@ hipError_t launch_bwd_fused_t(const BwdArgs& a, int groups, int ranges, int64_t 
   const float* sz = static_cast<const float*>(a.saved_z);
   const float* go = static_cast<const float*>(a.grad_out);
 #define IDW_BF(DP, DQ)                                                                          \
-  hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ>), grid, dim3(kWG), 0, st, a.data, a.n, \
+  hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ>), grid, dim3(kFNT), 0, st, a.data, a.n, \
                      a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den,     \
                      a.part_q, a.part_z)
   if (ndp && ndq)

@@ -171,15 +171,15 @@ def test_fused_and_separate_adjoint_sweeps(separate, dim, p):
 
 
 def test_fused_adjoint_accumulates_over_query_blocks():
-    # 300,000 data points in 3 ranges and 100,000 queries: each workgroup of the fused sweep
-    # folds several query blocks into its dz row.  The upstream gradient is non-zero on
-    # 300 scattered queries only, so the oracle needs just those 300 queries for the exact
-    # dz, dp and dq.
-    x, z, q = rand_case(32, 300000, 100000, 2)
+    # 1,000,000 data points in 16 ranges and 100,000 queries (98 blocks of 1,024): the 64
+    # workgroup groups of the fused sweep each fold one or two query blocks into their dz
+    # row.  The upstream gradient is non-zero on 150 scattered queries only, so the oracle
+    # needs just those queries for the exact dz, dp and dq.
+    x, z, q = rand_case(32, 1000000, 100000, 2)
     r = np.random.default_rng(33)
-    sel = np.sort(r.choice(len(q), size=300, replace=False))
+    sel = np.sort(r.choice(len(q), size=150, replace=False))
     g = np.zeros(len(q))
-    g[sel] = r.normal(size=300).astype(np.float32)
+    g[sel] = r.normal(size=150).astype(np.float32)
     d, qq = points(x, z, q, "soa", "f32")
     Z, D = api.forward(d, qq, 2.0, "f32")
     gt = torch.tensor(g, dtype=torch.float32, device="cuda")

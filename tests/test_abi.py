@@ -146,3 +146,35 @@ def test_batched_is_declared(lib):
     plan = ctypes.c_void_p()
     rc = lib.idw_batched_plan_create(None, 0, _lib.FP32, None, ctypes.byref(plan))
     assert rc != 0
+
+
+def test_timing_interface_without_device(lib):
+    ms, cnt = ctypes.c_double(-1.0), ctypes.c_int64(-1)
+    assert lib.idw_timing_enable(1) == 0
+    assert lib.idw_timing_read(_lib.T_FWD_SWEEP, ctypes.byref(ms), ctypes.byref(cnt)) == 0
+    assert ms.value == 0.0 and cnt.value == 0
+    assert lib.idw_timing_read(9, ctypes.byref(ms), ctypes.byref(cnt)) == _lib.IDW_EINVAL
+    assert lib.idw_timing_enable(0) == 0
+
+
+def test_batched_plan_argument_checks(lib):
+    plan = ctypes.c_void_p()
+    arr = (_lib.IdwInstance * 2)()
+    for k in range(2):
+        arr[k].data = _pts(1000, 2, _lib.AOAS)
+        arr[k].query = _pts(100, 2, _lib.AOAS, base=0x20000000)
+        arr[k].p = 2.0
+        arr[k].out_z = 0x30000000
+    # FP64 plans are not offered
+    assert lib.idw_batched_plan_create(arr, 2, _lib.FP64, None, ctypes.byref(plan)) == _lib.IDW_EUNSUPPORTED
+    # only aligned-AoS records
+    arr[1].data.layout = _lib.SOA
+    arr[1].query.layout = _lib.SOA
+    rc = lib.idw_batched_plan_create(arr, 2, _lib.FP32, None, ctypes.byref(plan))
+    assert rc == _lib.IDW_EUNSUPPORTED and b"instance 1" in lib.idw_last_error()
+    arr[1].data.layout = _lib.AOAS
+    arr[1].query.layout = _lib.AOAS
+    arr[0].p = -1.0
+    rc = lib.idw_batched_plan_create(arr, 2, _lib.FP32, None, ctypes.byref(plan))
+    assert rc == _lib.IDW_EINVAL and b"instance 0" in lib.idw_last_error()
+    assert not plan.value

@@ -1,0 +1,128 @@
+"""Accuracy report: the error of every workload against the FP64 oracle (and of the FP32
+path against the GPU FP64 path), as one JSON object per workload.
+
+Errors are |Z - Z_ref| / S with S = sum w|z| / sum w (the summation condition scale; the
+oracle reports it); gradients relative to their condition sums (see tests/).  Run on the
+MI355X machine:  python errors.py [--sample 512]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def _stats(e):
+    import numpy as np
+    e = np.asarray(e, dtype=np.float64)
+    return {"max": float(e.max()), "p99": float(np.quantile(e, 0.99)), "median": float(np.median(e)), "count": int(e.size)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sample", type=int, default=512)
+    args = ap.parse_args()
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1402_4986_amd import api, batched, workloads
+
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(2024)
+
+    def run(x, z, q, p, layout, prec):
+        d = api.Points.from_arrays(workloads.pack_data(x, z, layout, prec), len(x), x.shape[1], layout, dev)
+        qq = api.Points.from_arrays(workloads.pack_query(q, layout, prec), len(q), q.shape[1], layout, dev)
+        Z, D = api.forward(d, qq, p, prec)
+        torch.cuda.synchronize()
+        return Z.cpu().numpy().astype(np.float64), D.cpu().numpy(), d, qq, Z, D
+
+    out = {}
+    # plain2d FP64 10K: every query
+    c = workloads.WORKLOADS["plain2d_f64_10k"]
+    x, z, q, _ = workloads.plain2d(c["n"], c["m"], "f64", cfg=c["cfg"])
+    Z, *_ = run(x, z, q, 2.0, "aoas", "f64")
+    ref = oracle.forward(x, z, q, 2.0)
+    out["plain2d_f64_10k"] = {"fp64_vs_oracle": _stats(np.abs(Z - ref["Z"]) / ref["S"]), "queries": "all"}
+    print(json.dumps({"plain2d_f64_10k": out["plain2d_f64_10k"]}), flush=True)
+
+    # plain2d FP32 1M: sampled queries, FP32 and FP64 paths
+    c = workloads.WORKLOADS["plain2d_f32_1m"]
+    x, z, q, _ = workloads.plain2d(c["n"], c["m"], "f32", cfg=c["cfg"])
+    Z32, *_ = run(x, z, q, 2.0, "aoas", "f32")
+    Z64, *_ = run(x, z, q, 2.0, "aoas", "f64")
+    idx = np.sort(rng.choice(len(q), size=args.sample, replace=False))
+    ref = oracle.forward(x, z, q[idx], 2.0)
+    out["plain2d_f32_1m"] = {"fp32_vs_oracle": _stats(np.abs(Z32[idx] - ref["Z"]) / ref["S"]),
+                             "fp64_vs_oracle": _stats(np.abs(Z64[idx] - ref["Z"]) / ref["S"]),
+                             "fp32_vs_gpu_fp64_all_queries": _stats(np.abs(Z32 - Z64) / np.maximum(np.abs(Z64), 1e-30)),
+                             "queries": f"{args.sample} sampled"}
+    print(json.dumps({"plain2d_f32_1m": out["plain2d_f32_1m"]}), flush=True)
+
+    # mixture3d p = 2.5: FP32 path against the GPU FP64 path per query (all), oracle on
+    # samples and on every exact hit
+    c = workloads.WORKLOADS["mixture3d_p2.5_262k_1m"]
+    x, z, q, hits = workloads.mixture3d(c["n"], c["m"], c["hits"], "f32", cfg=c["cfg"])
+    Z32, *_ = run(x, z, q, 2.5, "aoas", "f32")
+    Z64, *_ = run(x, z, q, 2.5, "aoas", "f64")
+    idx = np.sort(rng.choice(len(q), size=args.sample, replace=False))
+    ref = oracle.forward(x, z, q[idx], 2.5)
+    refh = oracle.forward(x, z, q[hits], 2.5)
+    out["mixture3d_p2.5_262k_1m"] = {
+        "fp32_vs_gpu_fp64_all_queries": _stats(np.abs(Z32 - Z64) / np.maximum(np.abs(Z64), 1e-30)),
+        "fp32_vs_oracle": _stats(np.abs(Z32[idx] - ref["Z"]) / ref["S"]),
+        "fp64_vs_oracle": _stats(np.abs(Z64[idx] - ref["Z"]) / ref["S"]),
+        "exact_hits_bit_exact_fp32": bool(np.all(Z32[hits] == refh["Z"].astype(np.float32))),
+        "exact_hits_bit_exact_fp64": bool(np.all(Z64[hits] == refh["Z"])),
+        "queries": f"{args.sample} sampled + {len(hits)} hits"}
+    print(json.dumps({"mixture3d": out["mixture3d_p2.5_262k_1m"]}), flush=True)
+
+    # gradient workload: dq per sampled query at full size; dz/dp on the sample
+    c = workloads.WORKLOADS["plain2d_grad_f32_128k"]
+    x, z, q, t = workloads.plain2d(c["n"], c["m"], "f32", cfg=c["cfg"])
+    p = c["p"]
+    Zh, _, d, qq, Z, D = run(x, z, q, p, "hybrid", "f32")
+    g = ((2.0 / len(q)) * (Zh - t)).astype(np.float32).astype(np.float64)
+    dz, dp, dq = api.backward(d, qq, p, torch.tensor(g, dtype=torch.float32, device=dev), Z, D, "f32")
+    torch.cuda.synchronize()
+    idx = np.sort(rng.choice(len(q), size=args.sample, replace=False))
+    rb = oracle.backward(x, z, q[idx], p, g[idx])
+    eq = np.max(np.abs(dq.cpu().numpy()[idx] - rb["dq"]), axis=1) / rb["dq_cond"]
+    ds, qs = d, api.Points.from_arrays(workloads.pack_query(q[idx], "hybrid", "f32"), len(idx), 2, "hybrid", dev)
+    Zs, Ds = api.forward(ds, qs, p, "f32")
+    a, b, _ = api.backward(ds, qs, p, torch.tensor(g[idx], dtype=torch.float32, device=dev), Zs, Ds, "f32")
+    torch.cuda.synchronize()
+    ez = np.abs(a.cpu().numpy() - rb["dz"]) / rb["dz_scale"]
+    out["plain2d_grad_f32_128k"] = {"dq_vs_oracle": _stats(eq), "dz_vs_oracle": _stats(ez),
+                                    "dp_vs_oracle": abs(float(b) - rb["dp"]) / rb["dp_cond"],
+                                    "queries": f"{args.sample} sampled"}
+    print(json.dumps({"grad": out["plain2d_grad_f32_128k"]}), flush=True)
+
+    # batched x64: 64 sampled queries per instance
+    insts_np = workloads.batched(count=64, cfg=4)
+    insts = []
+    for i in insts_np:
+        insts.append(dict(data=torch.tensor(workloads.pack_data(i["x"], i["z"], "aoas", "f32")[0], device=dev),
+                          query=torch.tensor(workloads.pack_query(i["q"], "aoas", "f32")[0], device=dev),
+                          dim=i["dim"], p=i["p"], out_z=torch.empty(len(i["q"]), dtype=torch.float32, device=dev)))
+    plan = batched.BatchedPlan(insts)
+    plan.run()
+    torch.cuda.synchronize()
+    errs = []
+    for src, inst in zip(insts_np, insts):
+        k = rng.choice(len(src["q"]), size=min(64, len(src["q"])), replace=False)
+        r = oracle.forward(src["x"], src["z"], src["q"][k], src["p"])
+        errs.append(np.abs(inst["out_z"].cpu().numpy()[k] - r["Z"]) / r["S"])
+    plan.close()
+    out["batched_x64"] = {"fp32_vs_oracle": _stats(np.concatenate(errs)), "queries": "64 sampled per instance"}
+    print(json.dumps({"batched": out["batched_x64"]}), flush=True)
+    print(json.dumps({"errors": out}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

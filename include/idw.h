@@ -119,10 +119,13 @@ const char* idw_last_error(void);
 int idw_record_bytes(int32_t layout, int32_t dim, int32_t precision, int32_t is_data,
                      size_t bytes[4]);
 
-/* Device workspace needed by idw_forward and idw_backward for these point sets, with
- * `cfg` (nullable).  One workspace serves both calls.  Host only. */
+/* Device workspace needed for these point sets with `cfg` (nullable).  With no IDW_NEED_*
+ * bit in `flags` it is the forward's need; with any of them it covers idw_forward and
+ * idw_backward (one workspace then serves both; the forward uses a prefix of it).  The
+ * FP32 adjoint keeps per-range query partials and per-group data partials, about
+ * 1 GB at n = m = 2^20.  Host only. */
 int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t precision,
-                       const idw_config* cfg, size_t* bytes);
+                       uint32_t flags, const idw_config* cfg, size_t* bytes);
 
 /* Forward sweep (Eq. 1).
  *   data, query  point sets (device memory); query->n == m may be 0 (no-op).

@@ -69,7 +69,8 @@ def load(path: str | None = None):
         lib.idw_record_bytes.restype = ctypes.c_int
         lib.idw_record_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(sz)]
         lib.idw_workspace_size.restype = ctypes.c_int
-        lib.idw_workspace_size.argtypes = [P(IdwPoints), P(IdwPoints), ctypes.c_int32, P(IdwConfig), P(sz)]
+        lib.idw_workspace_size.argtypes = [P(IdwPoints), P(IdwPoints), ctypes.c_int32, ctypes.c_uint32, P(IdwConfig),
+                                           P(sz)]
         lib.idw_forward.restype = ctypes.c_int
         lib.idw_forward.argtypes = [P(IdwPoints), P(IdwPoints), ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
                                     vp, vp, vp, sz, vp, P(IdwConfig)]

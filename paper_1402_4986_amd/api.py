@@ -82,13 +82,15 @@ def _stream_handle(device) -> int:
 _ws_cache: dict = {}
 
 
-def workspace(data: Points, query: Points, precision: str, cfg: Optional[IdwConfig] = None) -> torch.Tensor:
-    """A device workspace large enough for forward and backward on these point sets
-    (cached per device and grown on demand)."""
+def workspace(data: Points, query: Points, precision: str, cfg: Optional[IdwConfig] = None,
+              backward: bool = True) -> torch.Tensor:
+    """A device workspace for the forward (backward=False) or for forward and backward on
+    these point sets (cached per device and grown on demand)."""
     lib = _lib.load()
     need = ctypes.c_size_t()
     dc, qc = data.c(), query.c()
-    check(lib.idw_workspace_size(ctypes.byref(dc), ctypes.byref(qc), _lib.PRECISION_CODES[precision],
+    flags = (_lib.NEED_DZ | _lib.NEED_DP | _lib.NEED_DQ) if backward else 0
+    check(lib.idw_workspace_size(ctypes.byref(dc), ctypes.byref(qc), _lib.PRECISION_CODES[precision], flags,
                                  ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(need)))
     key = (str(data.device),)
     ws = _ws_cache.get(key)
@@ -112,7 +114,7 @@ def forward(data: Points, query: Points, p: float, precision: str = "f32", exclu
         out_den = torch.empty(m, dtype=torch.float64, device=dev)
     cfg = _cfg(queries_per_lane, split)
     if ws is None:
-        ws = workspace(data, query, precision, cfg)
+        ws = workspace(data, query, precision, cfg, backward=False)
     dc, qc = data.c(), query.c()
     check(lib.idw_forward(ctypes.byref(dc), ctypes.byref(qc), float(p), _lib.PRECISION_CODES[precision],
                           _lib.EXCLUDE_SELF if exclude_self else 0, _ptr(out_z), _ptr(out_den), _ptr(ws),

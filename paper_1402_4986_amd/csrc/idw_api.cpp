@@ -212,6 +212,9 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   w.bcnt = take(sizeof(int) * static_cast<size_t>(nb + 1));
   w.list = take(sizeof(int) * static_cast<size_t>(m));
   w.part_f = take(w.split_f > 1 ? sizeof(double2) * static_cast<size_t>(w.split_f) * m : 0);
+  w.fpart = take(sizeof(double4) * kFixGrid);
+  w.fix_cmax = static_cast<int>(std::min<int64_t>(kFixGrid, std::max<int64_t>(1, cdiv(n, 4096))));
+  w.fwd_total = off;  // the forward uses only the sections above
   w.part_q = take(sizeof(double4) * static_cast<size_t>(std::max(w.split_q, w.fused_ranges)) * m);
   w.part_z = take(sizeof(double) * static_cast<size_t>(std::max(w.split_z, w.fused_groups)) * n);
   w.slot_coef = take(sizeof(double) * static_cast<size_t>(m));
@@ -219,11 +222,8 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   w.slot_dp = take(sizeof(double) * static_cast<size_t>(m));
   w.slot_z = take(sizeof(double) * static_cast<size_t>(m));
   w.slot_den = take(sizeof(double) * static_cast<size_t>(m));
-  w.fpart = take(sizeof(double4) * kFixGrid);
-  w.fix_cmax = static_cast<int>(std::min<int64_t>(kFixGrid, std::max<int64_t>(1, cdiv(n, 4096))));
   w.wg_dp = take(sizeof(double) * static_cast<size_t>(w.nwg_dp > 0 ? w.nwg_dp : 1));
   w.total = off;
-  (void)f64;
   return w;
 }
 
@@ -363,12 +363,13 @@ int idw_record_bytes(int32_t layout, int32_t dim, int32_t precision, int32_t is_
 }
 
 int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t precision,
-                       const idw_config* cfg, size_t* bytes) {
+                       uint32_t flags, const idw_config* cfg, size_t* bytes) {
   clear_error();
   if (!bytes) return fail(IDW_EINVAL, "bytes is null");
-  int rc = validate_common(data, query, 2.0, precision, 0);
+  int rc = validate_common(data, query, 2.0, precision, flags & ~IDW_EXCLUDE_SELF);
   if (rc) return rc;
-  *bytes = plan_workspace(data, query, precision, cfg).total;
+  const WsPlan w = plan_workspace(data, query, precision, cfg);
+  *bytes = (flags & (IDW_NEED_DZ | IDW_NEED_DP | IDW_NEED_DQ)) ? w.total : w.fwd_total;
   return IDW_OK;
 }
 
@@ -389,7 +390,7 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   if (m == 0) return IDW_OK;
   if (!out_z) return fail(IDW_EINVAL, "out_z is null");
   const WsPlan w = plan_workspace(data, query, precision, cfg);
-  rc = check_workspace(workspace, workspace_bytes, w.total);
+  rc = check_workspace(workspace, workspace_bytes, w.fwd_total);
   if (rc) return rc;
   rc = check_device();
   if (rc) return rc;

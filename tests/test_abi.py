@@ -127,7 +127,11 @@ def test_workspace_size_grows_with_queries(lib):
     for m in (1, 1000, 100000):
         q = _pts(m, 2, _lib.SOA)
         b = ctypes.c_size_t()
-        assert lib.idw_workspace_size(ctypes.byref(d), ctypes.byref(q), _lib.FP32, None, ctypes.byref(b)) == 0
+        assert lib.idw_workspace_size(ctypes.byref(d), ctypes.byref(q), _lib.FP32, 0, None, ctypes.byref(b)) == 0
+        f = ctypes.c_size_t()
+        assert lib.idw_workspace_size(ctypes.byref(d), ctypes.byref(q), _lib.FP32, _lib.NEED_DZ, None,
+                                      ctypes.byref(f)) == 0
+        assert f.value > b.value  # the adjoint needs more than the forward
         sizes.append(b.value)
     assert sizes[0] < sizes[1] < sizes[2]
 

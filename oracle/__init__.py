@@ -50,6 +50,9 @@ def _load():
             lib.idw_oracle_backward.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
                                                 ctypes.c_double, ip, dp, dp, dp, dp, dp, dp, dp, dp, dp]
             lib.idw_oracle_backward.restype = ctypes.c_int
+            lib.idw_oracle_backward_x.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
+                                                  ctypes.c_double, ip, dp, dp, dp]
+            lib.idw_oracle_backward_x.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -124,6 +127,27 @@ def backward(x, z, q, p, g, self_index=None):
         raise ValueError("oracle backward: invalid arguments")
     return {"dz": dz, "dp": float(dp[0]), "dq": dq, "dz_scale": dzs, "dp_scale": float(dps[0]),
             "dq_scale": dqs, "dp_cond": float(dpc[0]), "dq_cond": dqc}
+
+
+def backward_x(x, z, q, p, g, self_index=None):
+    """Adjoint with respect to the data coordinates: dict(dx [n, dim], dx_cond [n]).
+
+    dx_cond is the uncentred sum (|z_j| + |Z_i| in place of z_j - Z_i) that bounds how far
+    a relative perturbation of the values moves each row of dx.
+    """
+    lib = _load()
+    x, z, q, si = _prep(x, z, q, self_index)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
+    n, dim = x.shape
+    if g.shape[0] != q.shape[0]:
+        raise ValueError("oracle backward_x: g must be [m]")
+    dx = np.empty((n, dim))
+    dxc = np.empty(n)
+    rc = lib.idw_oracle_backward_x(n, dim, _d(x), _d(z), q.shape[0], _d(q), float(p), _i(si), _d(g),
+                                   _d(dx), _d(dxc))
+    if rc != 0:
+        raise ValueError("oracle backward_x: invalid arguments")
+    return {"dx": dx, "dx_cond": dxc}
 
 
 def loo_loss(x, z, p, idx=None):

@@ -100,8 +100,9 @@ def forward_decimal(x, z, q, p, prec: int = 60, self_index=None):
 def gradients_fd(x, z, q, p, g, prec: int = 80, h: str = "1e-28"):
     """Central finite differences of sum_i g_i Z_i in `prec`-digit decimal.
 
-    Returns dict(dz=[n], dp=scalar, dq=[m][dim]) as floats.  Truncation error is about
-    h^2 times the third derivative, far below double precision for h = 1e-28.
+    Returns dict(dz=[n], dp=scalar, dq=[m][dim], dx=[n][dim]) as floats.  Truncation
+    error is about h^2 times the third derivative, far below double precision for
+    h = 1e-28.
     """
     with localcontext() as ctx:
         ctx.prec = prec
@@ -137,4 +138,18 @@ def gradients_fd(x, z, q, p, g, prec: int = 80, h: str = "1e-28"):
                 qm[i] = tuple(b)
                 row.append(float((loss(X, V, qp, P) - loss(X, V, qm, P)) / (2 * H)))
             dq.append(row)
-        return {"dz": dz, "dp": dp, "dq": dq}
+        dx = []
+        for j in range(len(X)):
+            row = []
+            for k in range(len(X[j])):
+                xp = list(X)
+                xm = list(X)
+                a = list(X[j])
+                b = list(X[j])
+                a[k] += H
+                b[k] -= H
+                xp[j] = tuple(a)
+                xm[j] = tuple(b)
+                row.append(float((loss(xp, V, Q, P) - loss(xm, V, Q, P)) / (2 * H)))
+            dx.append(row)
+        return {"dz": dz, "dp": dp, "dq": dq, "dx": dx}

@@ -21,7 +21,12 @@
  *     dZ/dp   = -(1/D) sum_j w_j * (1/2) ln(r2_j) * (z_j - Z)
  *     dZ/dq   = -(p/D) sum_j (w_j / r2_j) * (z_j - Z) * (q - x_j)
  * and at an exact hit (h coincident points): dZ/dz_j = 1/h for each coincident j, and
- * dZ/dp = dZ/dq = 0.
+ * dZ/dp = dZ/dq = 0.  With respect to the data coordinates (w_j depends on x_j through
+ * r2_j = |q - x_j|^2 only):
+ *     dZ/dx_j = (p/D) (w_j / r2_j) * (z_j - Z) * (q - x_j)
+ * so that sum_j dZ/dx_j = -dZ/dq (Z depends on differences q - x_j only); at an exact hit
+ * Z is the mean of the coincident values whatever the other points' positions, and
+ * dZ/dx_j = 0 (the reading that matches dZ/dq = 0 there).
  *
  * Arrays: coordinates are row-major [count][dim] doubles; values are [n] doubles.
  * `self_index` (nullable) names, per query, one data index to leave out (leave-one-out).
@@ -197,5 +202,63 @@ int idw_oracle_backward(int64_t n, int dim, const double* x, const double* z, in
   if (dp_cond) dp_cond[0] = nval(&dpc);
   free(dzs);
   free(dza);
+  return 0;
+}
+
+/*
+ * Adjoint with respect to the data coordinates.  Given g[i] = dL/dZ_i, writes
+ *   dx[n*dim]   dL/dx_j = sum_i g_i dZ_i/dx_j
+ *               = sum_i (p g_i / D_i) (w_ij / r2_ij) (z_j - Z_i) (q_i - x_j)
+ * over the queries without an exact hit (a hit query contributes nothing), and, when
+ * given, dx_cond[n] = sum_i |p g_i / D_i| (w_ij / r2_ij) (|z_j| + |Z_i|) sum_k |q_ik - x_jk|,
+ * the uncentred sum that bounds the sensitivity of dx_j to the last bits of the values
+ * (as dq_cond does for dq).  Pairs left out by self_index are skipped.
+ */
+int idw_oracle_backward_x(int64_t n, int dim, const double* x, const double* z, int64_t m,
+                          const double* q, double p, const int64_t* self_index, const double* g,
+                          double* dx, double* dx_cond) {
+  if (n < 1 || m < 0 || (dim != 2 && dim != 3) || !(p > 0.0) || !x || !z || !dx ||
+      (m && (!q || !g)))
+    return -1;
+  nsum* acc = (nsum*)calloc((size_t)n * (size_t)dim, sizeof(nsum));
+  nsum* cnd = (nsum*)calloc((size_t)n, sizeof(nsum));
+  if (!acc || !cnd) {
+    free(acc);
+    free(cnd);
+    return -1;
+  }
+  for (int64_t i = 0; i < m; ++i) {
+    const double* qi = q + i * dim;
+    double Zi, Di;
+    int64_t h;
+    if (idw_oracle_forward(n, dim, x, z, 1, qi, p, self_index ? self_index + i : NULL, &Zi, &Di,
+                           NULL, &h) != 0) {
+      free(acc);
+      free(cnd);
+      return -1;
+    }
+    if (h > 0) continue;
+    const double a = p * g[i] / Di;
+    for (int64_t j = 0; j < n; ++j) {
+      if (self_index && self_index[i] == j) continue;
+      const double* xj = x + j * dim;
+      const double r2 = sqdist(qi, xj, dim);
+      const double f = weight(r2, p) / r2;
+      const double u = a * f * (z[j] - Zi);
+      double ea = 0.0;
+      for (int k = 0; k < dim; ++k) {
+        const double e = qi[k] - xj[k];
+        nadd(&acc[j * dim + k], u * e);
+        ea += fabs(e);
+      }
+      nadd(&cnd[j], fabs(a) * f * (fabs(z[j]) + fabs(Zi)) * ea);
+    }
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    for (int k = 0; k < dim; ++k) dx[j * dim + k] = nval(&acc[j * dim + k]);
+    if (dx_cond) dx_cond[j] = nval(&cnd[j]);
+  }
+  free(acc);
+  free(cnd);
   return 0;
 }

@@ -27,6 +27,8 @@ def test_analytic_gradient_matches_decimal_finite_differences(p, dim, hit):
     np.testing.assert_allclose(an["dz"], fd["dz"], rtol=1e-12, atol=1e-13)
     np.testing.assert_allclose(an["dq"], np.array(fd["dq"]), rtol=1e-11, atol=1e-12)
     assert an["dp"] == pytest.approx(fd["dp"], rel=1e-11, abs=1e-13)
+    ax = oracle.backward_x(x, z, q, float(p), g)
+    np.testing.assert_allclose(ax["dx"], np.array(fd["dx"]), rtol=1e-11, atol=1e-12)
 
 
 def test_value_gradient_sums_to_upstream_gradient():
@@ -93,3 +95,50 @@ def test_loo_loss_of_constant_field_is_zero():
     r = np.random.default_rng(26)
     x = r.random((40, 2))
     assert oracle.loo_loss(x, np.full(40, 2.0), 1.5) == pytest.approx(0.0, abs=1e-28)
+
+
+def test_data_coordinate_gradient_two_point_closed_form():
+    # q at the origin, x1 = (a, 0), x2 = (-b, 0), p = 2: Z = (z1 b^2 + z2 a^2) / (a^2 + b^2),
+    # so dZ/da = 2 a b^2 (z2 - z1) / (a^2 + b^2)^2 and dZ/db = 2 a^2 b (z1 - z2) / (a^2 + b^2)^2
+    # (x2's x-coordinate is -b); moving either point across the line changes Z only to
+    # second order.
+    a, b, z1, z2 = 0.3, 0.7, 1.25, -0.5
+    x = np.array([[a, 0.0], [-b, 0.0]])
+    z = np.array([z1, z2])
+    q = np.array([[0.0, 0.0]])
+    r = oracle.backward_x(x, z, q, 2.0, np.array([1.0]))
+    s2 = a * a + b * b
+    np.testing.assert_allclose(r["dx"][0], [2 * a * b * b * (z2 - z1) / s2 ** 2, 0.0], rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(r["dx"][1], [-(2 * a * a * b * (z1 - z2) / s2 ** 2), 0.0], rtol=1e-14, atol=1e-16)
+
+
+@pytest.mark.parametrize("hit", [False, True])
+def test_data_and_query_coordinate_gradients_cancel(hit):
+    # Z_i depends on the differences q_i - x_j only, so moving every point and every query
+    # together changes nothing: sum_j dL/dx_j = -sum_i dL/dq_i.
+    x, z, q, g = _case(25, n=70, m=25, dim=3, hit=hit)
+    bx = oracle.backward_x(x, z, q, 2.5, g)
+    bq = oracle.backward(x, z, q, 2.5, g)
+    np.testing.assert_allclose(bx["dx"].sum(axis=0), -bq["dq"].sum(axis=0), rtol=1e-11,
+                               atol=1e-13 * np.abs(bx["dx"]).sum())
+    assert np.all(bx["dx_cond"] >= np.abs(bx["dx"]).max(axis=1) - 1e-15)
+
+
+def test_constant_field_has_no_data_coordinate_gradient():
+    x, _, q, g = _case(26, n=40, m=9)
+    r = oracle.backward_x(x, np.full(40, -1.5), q, 3.0, g)
+    np.testing.assert_allclose(r["dx"], 0.0, atol=1e-12)
+
+
+def test_leave_one_out_data_gradient_matches_explicit_deletion():
+    # With queries at the data points and point i left out of query i, dL/dx_j collects
+    # from each query i != j the gradient of the interpolant built without point i.
+    x, z, _, _ = _case(27, n=12, m=1, dim=2)
+    g = np.random.default_rng(7).normal(size=12)
+    got = oracle.backward_x(x, z, x, 1.5, g, self_index=np.arange(12))["dx"]
+    want = np.zeros_like(x)
+    for i in range(12):
+        keep = np.array([j for j in range(12) if j != i])
+        r = oracle.backward_x(x[keep], z[keep], x[i:i + 1], 1.5, g[i:i + 1])
+        want[keep] += r["dx"]
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-15)

@@ -31,6 +31,10 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 FLOP/clk/
 #   data sweep  2 sub, mul + fma, rcp, fma (dz)                                    =  8
 #   fused adjoint: the query sweep plus fma (dz) on the same weight                =  18
 FLOP_PER_PAIR = {"fwd_sweep": 9, "bwd_query": 16, "bwd_data": 8, "bwd_fused": 18}
+# With the data-coordinate gradient (--need-dx): the fused sweep adds mul (a u) and one fma
+# per coordinate = 23; the separate data sweep computing dz and dx is 2 sub, mul + fma, rcp,
+# mul (a w), add (dz), mul (f), sub + mul (z - Z), 2 fma = 15.
+FLOP_PER_PAIR_DX = {"bwd_data": 15, "bwd_fused": 23}
 
 
 def kernel_source_hash() -> str:
@@ -85,6 +89,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=96)
     ap.add_argument("--separate-adjoint", action="store_true",
                     help="run the adjoint as separate query- and data-direction sweeps")
+    ap.add_argument("--need-dx", action="store_true",
+                    help="also compute the gradient with respect to the data coordinates")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one device-to-device copy of 512 MiB (counter calibration)")
     args = ap.parse_args()
@@ -115,13 +121,16 @@ def main():
 
     data, query = make(args.layout)
     gt = torch.tensor(g, dtype=torch.float32, device=dev)
-    ws = api.workspace(data, query, "f32")
+    ws = api.workspace(data, query, "f32", need_dx=args.need_dx)
+    if args.need_dx:
+        FLOP_PER_PAIR.update(FLOP_PER_PAIR_DX)
     Z = torch.empty(m, dtype=torch.float32, device=dev)
     D = torch.empty(m, dtype=torch.float64, device=dev)
 
     def step():
         api.forward(data, query, p, "f32", out_z=Z, out_den=D, ws=ws)
-        return api.backward(data, query, p, gt, Z, D, "f32", ws=ws, separate=args.separate_adjoint)
+        return api.backward(data, query, p, gt, Z, D, "f32", ws=ws, separate=args.separate_adjoint,
+                            need_dx=args.need_dx)
 
     for _ in range(args.warmup):
         step()
@@ -129,7 +138,7 @@ def main():
     _lib.check(lib.idw_timing_enable(1))
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        dz, dp, dq = step()
+        grads = step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = {}
@@ -160,7 +169,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": "plain2d_f32_1m", "n_data": n, "n_query": m, "dim": 2, "p": p,
                       "layout": args.layout, "precision": "fp32 sweep, fp64 ratio/fix-up",
-                      "grads": "dz,dp,dq"},
+                      "grads": "dz,dp,dq,dx" if args.need_dx else "dz,dp,dq"},
            "frac_fp32_peak_step": round(total_flop / (ms_step * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
            "kernels": kernels, "roofline": roofline}
 

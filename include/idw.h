@@ -75,6 +75,7 @@ enum { IDW_FP32 = 0, IDW_FP64 = 1 };
 #define IDW_NEED_DZ 0x2u      /* idw_backward: compute grad_z */
 #define IDW_NEED_DP 0x4u      /* idw_backward: compute grad_p */
 #define IDW_NEED_DQ 0x8u      /* idw_backward: compute grad_q */
+#define IDW_NEED_DX 0x10u     /* idw_backward: compute grad_x (data coordinates) */
 
 /* A point set.  n >= 0; dim 2 or 3; layout one of IDW_SOA..IDW_SOAOS; unused ptr[] slots
  * are ignored.  For data points n >= 1. */
@@ -121,9 +122,10 @@ int idw_record_bytes(int32_t layout, int32_t dim, int32_t precision, int32_t is_
 
 /* Device workspace needed for these point sets with `cfg` (nullable).  With no IDW_NEED_*
  * bit in `flags` it is the forward's need; with any of them it covers idw_forward and
- * idw_backward (one workspace then serves both; the forward uses a prefix of it).  The
- * FP32 adjoint keeps per-range query partials and per-group data partials, about
- * 1 GB at n = m = 2^20.  Host only. */
+ * idw_backward with those gradients (one workspace then serves both; the forward uses a
+ * prefix of it, and a backward without IDW_NEED_DX a prefix of the one with it).  The
+ * FP32 adjoint keeps per-range query partials and per-group data partials, about 1 GB at
+ * n = m = 2^20, plus dim x 512 MB there for IDW_NEED_DX.  Host only. */
 int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t precision,
                        uint32_t flags, const idw_config* cfg, size_t* bytes);
 
@@ -147,16 +149,20 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
  *   grad_z [n]       dL/dz_j   (element type of precision)   if flags & IDW_NEED_DZ
  *   grad_p [1]       dL/dp     (double, device)              if flags & IDW_NEED_DP
  *   grad_q [m*dim]   dL/dq_i   row-major, element type       if flags & IDW_NEED_DQ
- * saved_z / saved_den are idw_forward's out_z / out_den for the same inputs and p.  The
- * formulas are those of Eq. 1 differentiated: dZ_i/dz_j = w_ij / D_i,
+ *   grad_x [n*dim]   dL/dx_j   row-major, element type       if flags & IDW_NEED_DX
+ * (pointers of gradients not requested are ignored and may be null).  saved_z / saved_den
+ * are idw_forward's out_z / out_den for the same inputs and p.  The formulas are those of
+ * Eq. 1 differentiated: dZ_i/dz_j = w_ij / D_i,
  * dZ_i/dp = -(1/D_i) sum_j w_ij (1/2) ln(d_ij^2) (z_j - Z_i),
- * dZ_i/dq_i = -(p/D_i) sum_j (w_ij / d_ij^2) (z_j - Z_i)(q_i - x_j); at an exact hit with h
+ * dZ_i/dq_i = -(p/D_i) sum_j (w_ij / d_ij^2) (z_j - Z_i)(q_i - x_j),
+ * dZ_i/dx_j = (p/D_i)(w_ij / d_ij^2)(z_j - Z_i)(q_i - x_j); at an exact hit with h
  * coincident points, dZ_i/dz_j = 1/h for each of them and the other terms are 0.
  * Queries within 1e-6 of the extent of a data point are handled in FP64. */
 int idw_backward(const idw_points* data, const idw_points* query, double p, int32_t precision,
                  uint32_t flags, const void* grad_out, const void* saved_z,
                  const double* saved_den, void* grad_z, double* grad_p, void* grad_q,
-                 void* workspace, size_t workspace_bytes, void* stream, const idw_config* cfg);
+                 void* grad_x, void* workspace, size_t workspace_bytes, void* stream,
+                 const idw_config* cfg);
 
 /* ---- Kernel timing (benchmarks).  When enabled, idw_forward / idw_backward bracket each
  * all-pairs sweep kernel with HIP events recorded on the launch stream.  Not for use

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libidw.so")
 IDW_OK, IDW_EINVAL, IDW_EDEVICE, IDW_ENOMEM, IDW_EUNSUPPORTED, IDW_EWORKSPACE = range(6)
 SOA, AOS, AOAS, HYBRID, SOAOS = range(5)
 FP32, FP64 = 0, 1
-EXCLUDE_SELF, NEED_DZ, NEED_DP, NEED_DQ = 0x1, 0x2, 0x4, 0x8
+EXCLUDE_SELF, NEED_DZ, NEED_DP, NEED_DQ, NEED_DX = 0x1, 0x2, 0x4, 0x8, 0x10
 
 LAYOUT_CODES = {"soa": SOA, "aos": AOS, "aoas": AOAS, "hybrid": HYBRID, "soaos": SOAOS}
 PRECISION_CODES = {"f32": FP32, "f64": FP64}
@@ -76,7 +76,7 @@ def load(path: str | None = None):
                                     vp, vp, vp, sz, vp, P(IdwConfig)]
         lib.idw_backward.restype = ctypes.c_int
         lib.idw_backward.argtypes = [P(IdwPoints), P(IdwPoints), ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
-                                     vp, vp, vp, vp, vp, vp, vp, sz, vp, P(IdwConfig)]
+                                     vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, P(IdwConfig)]
         lib.idw_timing_enable.restype = ctypes.c_int
         lib.idw_timing_enable.argtypes = [ctypes.c_int32]
         lib.idw_timing_read.restype = ctypes.c_int

@@ -83,13 +83,16 @@ _ws_cache: dict = {}
 
 
 def workspace(data: Points, query: Points, precision: str, cfg: Optional[IdwConfig] = None,
-              backward: bool = True) -> torch.Tensor:
+              backward: bool = True, need_dx: bool = False) -> torch.Tensor:
     """A device workspace for the forward (backward=False) or for forward and backward on
-    these point sets (cached per device and grown on demand)."""
+    these point sets, with room for the data-coordinate gradient when need_dx (cached per
+    device and grown on demand)."""
     lib = _lib.load()
     need = ctypes.c_size_t()
     dc, qc = data.c(), query.c()
     flags = (_lib.NEED_DZ | _lib.NEED_DP | _lib.NEED_DQ) if backward else 0
+    if backward and need_dx:
+        flags |= _lib.NEED_DX
     check(lib.idw_workspace_size(ctypes.byref(dc), ctypes.byref(qc), _lib.PRECISION_CODES[precision], flags,
                                  ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(need)))
     key = (str(data.device),)
@@ -125,8 +128,9 @@ def forward(data: Points, query: Points, p: float, precision: str = "f32", exclu
 def backward(data: Points, query: Points, p: float, grad_out: torch.Tensor, saved_z: torch.Tensor,
              saved_den: torch.Tensor, precision: str = "f32", need_dz: bool = True, need_dp: bool = True,
              need_dq: bool = True, exclude_self: bool = False, ws: Optional[torch.Tensor] = None,
-             separate: bool = False):
-    """(dz[n] or None, dp (0-d float64 tensor) or None, dq[m, dim] or None).
+             separate: bool = False, need_dx: bool = False):
+    """(dz[n] or None, dp (0-d float64 tensor) or None, dq[m, dim] or None), followed by
+    dx[n, dim] when need_dx (the gradient with respect to the data coordinates).
 
     separate=True runs the query-direction and data-direction sweeps as two kernels
     instead of the fused FP32 sweep (for comparison)."""
@@ -137,10 +141,11 @@ def backward(data: Points, query: Points, p: float, grad_out: torch.Tensor, save
     dz = torch.empty(n, dtype=dt, device=dev) if need_dz else None
     dp = torch.empty((), dtype=torch.float64, device=dev) if need_dp else None
     dq = torch.empty((m, dim), dtype=dt, device=dev) if need_dq else None
+    dx = torch.empty((n, dim), dtype=dt, device=dev) if need_dx else None
     flags = (_lib.EXCLUDE_SELF if exclude_self else 0) | (_lib.NEED_DZ if need_dz else 0) \
-        | (_lib.NEED_DP if need_dp else 0) | (_lib.NEED_DQ if need_dq else 0)
+        | (_lib.NEED_DP if need_dp else 0) | (_lib.NEED_DQ if need_dq else 0) | (_lib.NEED_DX if need_dx else 0)
     if ws is None:
-        ws = workspace(data, query, precision)
+        ws = workspace(data, query, precision, need_dx=need_dx)
     dc, qc = data.c(), query.c()
     cfg = None
     if separate:
@@ -148,8 +153,10 @@ def backward(data: Points, query: Points, p: float, grad_out: torch.Tensor, save
         cfg.separate_adjoint = 1
     check(lib.idw_backward(ctypes.byref(dc), ctypes.byref(qc), float(p), _lib.PRECISION_CODES[precision], flags,
                            _ptr(grad_out.contiguous()), _ptr(saved_z), _ptr(saved_den), _ptr(dz), _ptr(dp),
-                           _ptr(dq), _ptr(ws), ws.numel(), _stream_handle(dev),
+                           _ptr(dq), _ptr(dx), _ptr(ws), ws.numel(), _stream_handle(dev),
                            ctypes.byref(cfg) if cfg is not None else None))
+    if need_dx:
+        return dz, dp, dq, dx
     return dz, dp, dq
 
 
@@ -163,7 +170,7 @@ def _precision_of(t: torch.Tensor) -> str:
 
 class IDWFunction(torch.autograd.Function):
     """Z = IDW(X, z, Q, p) with X [n, dim] data coordinates, z [n] values, Q [m, dim]
-    queries and p a 0-d tensor.  Gradients flow to z, Q and p (not to X)."""
+    queries and p a 0-d tensor.  Gradients flow to X, z, Q and p."""
 
     @staticmethod
     def forward(ctx, X, z, Q, p, exclude_self=False):
@@ -183,15 +190,15 @@ class IDWFunction(torch.autograd.Function):
     def backward(ctx, gZ):
         X, z, Q, Z, D = ctx.saved_tensors
         need_x, need_z, need_q, need_p = ctx.needs_input_grad[:4]
-        if need_x:
-            raise NotImplementedError("the gradient with respect to data coordinates is not provided")
-        if not (need_z or need_q or need_p):
+        if not (need_x or need_z or need_q or need_p):
             return None, None, None, None, None
         data = Points.hybrid(X, z)
         query = Points.hybrid(Q)
-        dz, dp, dq = backward(data, query, ctx.pv, gZ.to(Z.dtype).contiguous(), Z, D, ctx.prec, need_dz=need_z,
-                              need_dp=need_p, need_dq=need_q, exclude_self=ctx.excl)
-        return None, dz, dq, (dp.to(ctx.p_dtype) if dp is not None else None), None
+        r = backward(data, query, ctx.pv, gZ.to(Z.dtype).contiguous(), Z, D, ctx.prec, need_dz=need_z,
+                     need_dp=need_p, need_dq=need_q, exclude_self=ctx.excl, need_dx=need_x)
+        dz, dp, dq = r[:3]
+        dx = r[3] if need_x else None
+        return dx, dz, dq, (dp.to(ctx.p_dtype) if dp is not None else None), None
 
 
 def interpolate(X: torch.Tensor, z: torch.Tensor, Q: torch.Tensor, p=2.0) -> torch.Tensor:

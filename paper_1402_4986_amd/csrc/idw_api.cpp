@@ -137,7 +137,7 @@ int validate_common(const idw_points* data, const idw_points* query, double p, i
     return fail(IDW_EUNSUPPORTED, "query layout must match the data layout (AoS and hybrid "
                                   "query records are the same)");
   if (!(p > 0.0) || !(p <= 64.0)) return fail(IDW_EINVAL, "p must satisfy 0 < p <= 64");
-  if (flags & ~(IDW_EXCLUDE_SELF | IDW_NEED_DZ | IDW_NEED_DP | IDW_NEED_DQ))
+  if (flags & ~(IDW_EXCLUDE_SELF | IDW_NEED_DZ | IDW_NEED_DP | IDW_NEED_DQ | IDW_NEED_DX))
     return fail(IDW_EINVAL, "unknown flag bits 0x%x", flags);
   if ((flags & IDW_EXCLUDE_SELF) && query->n != data->n)
     return fail(IDW_EINVAL, "IDW_EXCLUDE_SELF needs as many queries as data points");
@@ -207,7 +207,7 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
     return at;
   };
   w.hdr = take(512);
-  w.bbox = take(sizeof(double) * 6 * static_cast<size_t>(w.nbbox));
+  w.bbox = take(sizeof(double) * kBboxStride * static_cast<size_t>(w.nbbox));
   w.flag = take(static_cast<size_t>(m));
   w.bcnt = take(sizeof(int) * static_cast<size_t>(nb + 1));
   w.list = take(sizeof(int) * static_cast<size_t>(m));
@@ -224,6 +224,9 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   w.slot_den = take(sizeof(double) * static_cast<size_t>(m));
   w.wg_dp = take(sizeof(double) * static_cast<size_t>(w.nwg_dp > 0 ? w.nwg_dp : 1));
   w.total = off;
+  w.part_x = take(sizeof(double) * static_cast<size_t>(std::max(w.split_z, w.fused_groups)) * n *
+                  static_cast<size_t>(data->dim));
+  w.total_x = off;
   return w;
 }
 
@@ -234,19 +237,16 @@ struct LayoutFns {
   hipError_t (*bbox)(const DevPts&, int64_t, int, bool, double*, int, hipStream_t);
   hipError_t (*bwd_query)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_data)(const BwdArgs&, bool, hipStream_t);
+  hipError_t (*bwd_datax)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_fixup)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_fused)(const BwdArgs&, hipStream_t);
 };
 
-static const LayoutFns kFns[5] = {
-    {fwd_sweep_soa, fwd_fixup_soa, bbox_soa, bwd_query_soa, bwd_data_soa, bwd_fixup_soa, bwd_fused_soa},
-    {fwd_sweep_aos, fwd_fixup_aos, bbox_aos, bwd_query_aos, bwd_data_aos, bwd_fixup_aos, bwd_fused_aos},
-    {fwd_sweep_aoas, fwd_fixup_aoas, bbox_aoas, bwd_query_aoas, bwd_data_aoas, bwd_fixup_aoas, bwd_fused_aoas},
-    {fwd_sweep_hybrid, fwd_fixup_hybrid, bbox_hybrid, bwd_query_hybrid, bwd_data_hybrid,
-     bwd_fixup_hybrid, bwd_fused_hybrid},
-    {fwd_sweep_soaos, fwd_fixup_soaos, bbox_soaos, bwd_query_soaos, bwd_data_soaos,
-     bwd_fixup_soaos, bwd_fused_soaos},
-};
+#define IDW_FNS(NAME)                                                                   \
+  {fwd_sweep_##NAME, fwd_fixup_##NAME, bbox_##NAME,      bwd_query_##NAME, bwd_data_##NAME, \
+   bwd_datax_##NAME, bwd_fixup_##NAME, bwd_fused_##NAME}
+static const LayoutFns kFns[5] = {IDW_FNS(soa), IDW_FNS(aos), IDW_FNS(aoas), IDW_FNS(hybrid), IDW_FNS(soaos)};
+#undef IDW_FNS
 
 const LayoutFns& fns(int layout) { return kFns[layout]; }
 
@@ -369,7 +369,9 @@ int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t 
   int rc = validate_common(data, query, 2.0, precision, flags & ~IDW_EXCLUDE_SELF);
   if (rc) return rc;
   const WsPlan w = plan_workspace(data, query, precision, cfg);
-  *bytes = (flags & (IDW_NEED_DZ | IDW_NEED_DP | IDW_NEED_DQ)) ? w.total : w.fwd_total;
+  *bytes = (flags & IDW_NEED_DX) ? w.total_x
+           : (flags & (IDW_NEED_DZ | IDW_NEED_DP | IDW_NEED_DQ)) ? w.total
+                                                                 : w.fwd_total;
   return IDW_OK;
 }
 
@@ -439,20 +441,23 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
 int idw_backward(const idw_points* data, const idw_points* query, double p, int32_t precision,
                  uint32_t flags, const void* grad_out, const void* saved_z,
                  const double* saved_den, void* grad_z, double* grad_p, void* grad_q,
-                 void* workspace, size_t workspace_bytes, void* stream, const idw_config* cfg) {
+                 void* grad_x, void* workspace, size_t workspace_bytes, void* stream,
+                 const idw_config* cfg) {
   clear_error();
   int rc = validate_common(data, query, p, precision, flags);
   if (rc) return rc;
   const bool ndz = flags & IDW_NEED_DZ, ndp = flags & IDW_NEED_DP, ndq = flags & IDW_NEED_DQ;
-  if (!(ndz || ndp || ndq)) return fail(IDW_EINVAL, "no gradient requested (IDW_NEED_* flags)");
+  const bool ndx = flags & IDW_NEED_DX;
+  if (!(ndz || ndp || ndq || ndx)) return fail(IDW_EINVAL, "no gradient requested (IDW_NEED_* flags)");
   if (ndz && !grad_z) return fail(IDW_EINVAL, "IDW_NEED_DZ set but grad_z is null");
   if (ndp && !grad_p) return fail(IDW_EINVAL, "IDW_NEED_DP set but grad_p is null");
   if (ndq && !grad_q && query->n > 0) return fail(IDW_EINVAL, "IDW_NEED_DQ set but grad_q is null");
+  if (ndx && !grad_x) return fail(IDW_EINVAL, "IDW_NEED_DX set but grad_x is null");
   const int64_t m = query->n;
   if (m > 0 && (!grad_out || !saved_z || !saved_den))
     return fail(IDW_EINVAL, "grad_out, saved_z and saved_den are required");
   const WsPlan w = plan_workspace(data, query, precision, cfg);
-  rc = check_workspace(workspace, workspace_bytes, w.total);
+  rc = check_workspace(workspace, workspace_bytes, ndx ? w.total_x : w.total);
   if (rc) return rc;
   rc = check_device();
   if (rc) return rc;
@@ -461,6 +466,9 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
   char* ws = static_cast<char*>(workspace);
   if (m == 0) {  // no queries: every gradient is zero
     if (ndz && (rc = check_hip(fill_zero(grad_z, static_cast<size_t>(data->n) * elem(precision), st), "fill")))
+      return rc;
+    if (ndx && (rc = check_hip(fill_zero(grad_x, static_cast<size_t>(data->n) * data->dim * elem(precision), st),
+                               "fill")))
       return rc;
     if (ndp && (rc = check_hip(fill_zero(grad_p, sizeof(double), st), "fill"))) return rc;
     return IDW_OK;
@@ -489,6 +497,8 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
   a.saved_den = saved_den;
   a.grad_z = ndz ? grad_z : nullptr;
   a.grad_q = ndq ? grad_q : nullptr;
+  a.grad_x = ndx ? grad_x : nullptr;
+  a.part_x = ndx ? reinterpret_cast<double*>(ws + w.part_x) : nullptr;
   a.wg_dp = ndp ? reinterpret_cast<double*>(ws + w.wg_dp) : nullptr;
   a.list = reinterpret_cast<const int*>(ws + w.list);
   a.count = reinterpret_cast<const int*>(ws + w.hdr + 256);
@@ -509,8 +519,11 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
                                     reinterpret_cast<int*>(ws + w.hdr + 256), st),
                       "compaction")))
     return rc;
-  const bool fused = !f64 && ndz && (ndp || ndq) && w.fused_groups > 0 && !(cfg && cfg->separate_adjoint);
-  if (fused) {  // one FP32 sweep for dp/dq and dz
+  // The fused FP32 sweep pays off when both directions are needed: dz or dx with dp or dq,
+  // or dx alone (its per-pair factors are those of dq).
+  const bool fused = !f64 && (ndx || (ndz && (ndp || ndq))) && w.fused_groups > 0 &&
+                     !(cfg && cfg->separate_adjoint);
+  if (fused) {  // one FP32 sweep for dp/dq and dz (and dx)
     a.fused_groups = w.fused_groups;
     a.fused_ranges = w.fused_ranges;
     a.fused_chunk = w.fused_chunk;
@@ -519,15 +532,21 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
     BwdArgs b = a;
     b.split_q = w.fused_ranges;
     b.split_z = w.fused_groups;
-    if ((rc = check_hip(bwd_qmerge(b, f64, st), "query merge"))) return rc;
-    if ((rc = check_hip(bwd_zmerge(b, f64, st), "data merge"))) return rc;
+    if ((ndp || ndq) && (rc = check_hip(bwd_qmerge(b, f64, st), "query merge"))) return rc;
+    if (ndz && (rc = check_hip(bwd_zmerge(b, f64, st), "data merge"))) return rc;
+    if (ndx && (rc = check_hip(bwd_xmerge(b, w.fused_groups, f64, st), "data-coordinate merge"))) return rc;
   } else {
     if (ndp || ndq) {
       if ((rc = check_hip(timed(IDW_T_BWD_QUERY, st, [&] { return F.bwd_query(a, f64, st); }), "query sweep")))
         return rc;
       if ((rc = check_hip(bwd_qmerge(a, f64, st), "query merge"))) return rc;
     }
-    if (ndz) {
+    if (ndx) {  // one data-direction sweep yields dz and dx
+      if ((rc = check_hip(timed(IDW_T_BWD_DATA, st, [&] { return F.bwd_datax(a, f64, st); }), "data sweep")))
+        return rc;
+      if (ndz && (rc = check_hip(bwd_zmerge(a, f64, st), "data merge"))) return rc;
+      if ((rc = check_hip(bwd_xmerge(a, w.split_z, f64, st), "data-coordinate merge"))) return rc;
+    } else if (ndz) {
       if ((rc = check_hip(timed(IDW_T_BWD_DATA, st, [&] { return F.bwd_data(a, f64, st); }), "data sweep")))
         return rc;
       if ((rc = check_hip(bwd_zmerge(a, f64, st), "data merge"))) return rc;

@@ -25,6 +25,8 @@ struct WsPlan {
   size_t slot_coef = 0, slot_hits = 0, slot_dp = 0, slot_z = 0, slot_den = 0, fpart = 0, wg_dp = 0;
   size_t fwd_total = 0;  // bytes the forward needs (a prefix of the full layout)
   size_t total = 0;      // bytes forward + backward need
+  size_t part_x = 0;     // data-coordinate partials, after everything else
+  size_t total_x = 0;    // bytes forward + backward need with the data-coordinate gradient
   int fix_cmax = 1;
 };
 

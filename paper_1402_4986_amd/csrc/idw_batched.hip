@@ -58,6 +58,7 @@ __global__ __launch_bounds__(kWG) void kb_bbox(const BInst* __restrict__ inst, d
   const BInst I = inst[i];
   double mn[3] = {__builtin_huge_val(), __builtin_huge_val(), __builtin_huge_val()};
   double mx[3] = {-__builtin_huge_val(), -__builtin_huge_val(), -__builtin_huge_val()};
+  double vm = 0.0;
   for (int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; j < I.n;
        j += static_cast<int64_t>(gridDim.x) * kWG) {
     const float4 r = I.data[j];
@@ -66,8 +67,18 @@ __global__ __launch_bounds__(kWG) void kb_bbox(const BInst* __restrict__ inst, d
       mn[d] = fmin(mn[d], c[d]);
       mx[d] = fmax(mx[d], c[d]);
     }
+    vm = fmax(vm, fabs(static_cast<double>(I.dim == 3 ? r.w : r.z)));
   }
   const int t = threadIdx.x;
+  double* rec = part + (static_cast<int64_t>(i) * gridDim.x + blockIdx.x) * kBboxStride;
+  red[t] = vm;
+  __syncthreads();
+  for (int s = kWG / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) rec[6] = red[0];
+  __syncthreads();
   for (int d = 0; d < 3; ++d) {
     for (int pass = 0; pass < 2; ++pass) {
       red[t] = pass ? mx[d] : mn[d];
@@ -76,7 +87,7 @@ __global__ __launch_bounds__(kWG) void kb_bbox(const BInst* __restrict__ inst, d
         if (t < s) red[t] = pass ? fmax(red[t], red[t + s]) : fmin(red[t], red[t + s]);
         __syncthreads();
       }
-      if (t == 0) part[(static_cast<int64_t>(i) * gridDim.x + blockIdx.x) * 6 + pass * 3 + d] = red[0];
+      if (t == 0) rec[pass * 3 + d] = red[0];
       __syncthreads();
     }
   }
@@ -88,27 +99,18 @@ __global__ __launch_bounds__(64) void kb_bbox_final(const BInst* __restrict__ in
   const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= count) return;
   const BInst I = inst[i];
-  double ext = 0.0;
+  const double* rec = part + static_cast<int64_t>(i) * nb * kBboxStride;
+  double ext = 0.0, vm = 0.0;
   for (int d = 0; d < I.dim; ++d) {
     double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
     for (int b = 0; b < nb; ++b) {
-      mn = fmin(mn, part[(static_cast<int64_t>(i) * nb + b) * 6 + d]);
-      mx = fmax(mx, part[(static_cast<int64_t>(i) * nb + b) * 6 + 3 + d]);
+      mn = fmin(mn, rec[b * kBboxStride + d]);
+      mx = fmax(mx, rec[b * kBboxStride + 3 + d]);
     }
     ext = fmax(ext, mx - mn);
   }
-  if (!(ext > 0.0) || !(ext < __builtin_huge_val())) ext = 1.0;
-  int e = 0;
-  (void)frexp(ext, &e);
-  const double s = ldexp(1.0, -e);
-  double* h = hdr + static_cast<int64_t>(i) * 8;
-  h[H_SCALE] = s;
-  h[H_THR_S] = pow(1e-6 * ext * s, -I.p);
-  h[H_LO_S] = ldexp(1.0, -60);
-  h[H_DEN_UNIT] = pow(s, I.p);
-  h[H_THR_U] = h[H_THR_S] * h[H_DEN_UNIT];
-  h[H_LO_U] = h[H_LO_S] * h[H_DEN_UNIT];
-  h[H_EXTENT] = ext;
+  for (int b = 0; b < nb; ++b) vm = fmax(vm, rec[b * kBboxStride + 6]);
+  fill_header(hdr + static_cast<int64_t>(i) * 8, ext, vm, I.p, true);
 }
 
 // ---- persistent sweep ----
@@ -452,7 +454,7 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
   const int64_t mt = std::max<int64_t>(P->mtot, 1);
   const int64_t nb = (mt + kCountBlock - 1) / kCountBlock;
   P->o_hdr = take(sizeof(double) * 8 * count);
-  P->o_bbox = take(sizeof(double) * 6 * kBboxBlocks * count);
+  P->o_bbox = take(sizeof(double) * kBboxStride * kBboxBlocks * count);
   P->o_counter = take(sizeof(int) * 4);
   P->o_count = take(sizeof(int) * 4);
   P->o_part = take(sizeof(double2) * std::max<int64_t>(P->part_elems, 1));

@@ -16,7 +16,11 @@
 //    LDS; accumulates dz_j = sum_i a_i w_ij;
 //  * FP64 fix-up for flagged queries (exact hits and near-coincident points): a per-query
 //    workgroup recomputes Z, D, dq and dp exactly, and a data-parallel pass adds their dz
-//    contributions in ascending query order.
+//    (and dx) contributions in ascending query order.
+// The gradient with respect to the data coordinates,
+//   dZ_i/dx_j = (p/D_i)(w_ij / r2_ij)(z_j - Z_i)(q_i - x_j),
+// is a data-direction sum like dz; it has its own data sweep (k_bwd_datax, which also
+// yields dz) and rides the fused FP32 sweep.
 #pragma once
 
 #include <math.h>
@@ -393,6 +397,172 @@ __global__ __launch_bounds__(kWG) void k_bwd_zmerge(const double* __restrict__ p
   grad_z[j] = static_cast<T>(h + l);
 }
 
+// Coordinate given to queries that a data-direction sweep leaves out (flagged for the FP64
+// fix-up, or past the end of the query chunk): far from every scaled data point, with r2
+// and every product of the pair terms finite, so that their zero factor a = 0 gives exact
+// zeros (an infinite coordinate would turn 0 * (q - x) into NaN).
+template <typename T>
+__device__ __forceinline__ T farT() {
+  return static_cast<T>(0x1p60);
+}
+
+// Data sweep with the data-coordinate gradient: lanes own Q data points (scaled coordinates
+// and value), query tiles (q_i, a_i) and Z_i are broadcast from LDS.  Accumulates, with
+// blocked TwoSum as the data sweep,
+//   dz_j = sum_i a_i w_ij     and     X_j = sum_i a_i (w_ij / r2_ij)(z_j - Z_i)(q_i - x_j)
+// over query chunk c: part_z[c * n + j] and part_x[(c * n + j) * DIM + e] (double).
+template <typename T, int DIM, int L, int PM, int Q, int UNR = 2>
+__global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPts query, int64_t m,
+                                                   int64_t chunk, T nhp, unsigned flags,
+                                                   const double* __restrict__ hdr,
+                                                   const T* __restrict__ grad_out,
+                                                   const T* __restrict__ saved_z,
+                                                   const double* __restrict__ saved_den,
+                                                   double* __restrict__ part_z,
+                                                   double* __restrict__ part_x) {
+  __shared__ P4<T> tile[2][kTile];
+  __shared__ T ztl[2][kTile];
+  const int tid = threadIdx.x;
+  const int64_t x0 = static_cast<int64_t>(blockIdx.x) * (kWG * Q);
+  const int64_t ib = static_cast<int64_t>(blockIdx.y) * chunk;
+  const int64_t ie = (ib + chunk < m) ? ib + chunk : m;
+  const T s = static_cast<T>(hdr[H_SCALE]);
+  const double thr = hdr[H_THR_U], lo = hdr[H_LO_U], unit = hdr[H_DEN_UNIT];
+  const bool excl = (flags & 1u) != 0;
+
+  T xc[Q][3], xv[Q];
+  int64_t xj[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    xj[k] = x0 + tid + static_cast<int64_t>(k) * kWG;
+    T c[3] = {T(0), T(0), T(0)}, v = T(0);
+    if (xj[k] < n) Loader<T, DIM, L>::data(data, xj[k], c, v);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xc[k][d] = c[d] * s;
+    xv[k] = v;
+  }
+  T zh[Q], zl[Q], xh[Q][3], xl[Q][3];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    zh[k] = zl[k] = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xh[k][d] = xl[k][d] = T(0);
+  }
+
+  T rc[2][3], ra[2], rz[2];
+  bool live[2];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t i = ib + static_cast<int64_t>(t) * kTile + u * kWG + tid;
+      rc[u][0] = rc[u][1] = rc[u][2] = T(0);
+      ra[u] = rz[u] = T(0);
+      live[u] = false;
+      if (i < ie) {
+        const double D = saved_den[i];
+        if (D <= thr && D > lo) {  // flagged queries are left to the FP64 fix-up
+          Loader<T, DIM, L>::query(query, i, rc[u]);
+          ra[u] = static_cast<T>(static_cast<double>(grad_out[i]) / (D / unit));
+          rz[u] = saved_z[i];
+          live[u] = true;
+        }
+      }
+    }
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      P4<T> r = stage<T, DIM>(rc[u], ra[u], s);
+      if (!live[u]) {
+        r.x = r.y = farT<T>();
+        if constexpr (DIM == 3) r.z = farT<T>();
+      }
+      tile[b][u * kWG + tid] = r;
+      ztl[b][u * kWG + tid] = rz[u];
+    }
+  };
+
+  const int ntiles = static_cast<int>((ie - ib + kTile - 1) / kTile);
+  fetch(0);
+  put(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) fetch(t + 1);
+    const int64_t it = ib + static_cast<int64_t>(t) * kTile;
+    const bool diag = excl && it < x0 + kWG * Q && x0 < it + kTile;
+    const P4<T>* tl = tile[t & 1];
+    const T* zt = ztl[t & 1];
+    for (int c0 = 0; c0 < kTile; c0 += 64) {
+      T az[Q], ax[Q][3];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) az[k] = ax[k][0] = ax[k][1] = ax[k][2] = T(0);
+#pragma unroll UNR
+      for (int ii = 0; ii < 64; ++ii) {
+        const P4<T> d = tl[c0 + ii];
+        const T zi = zt[c0 + ii];
+        const T a = (DIM == 3) ? d.w : d.z;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          const T e0 = d.x - xc[k][0];  // q - x
+          const T e1 = d.y - xc[k][1];
+          T e2 = T(0);
+          T r2 = e0 * e0;
+          r2 = fmaT(e1, e1, r2);
+          if constexpr (DIM == 3) {
+            e2 = d.z - xc[k][2];
+            r2 = fmaT(e2, e2, r2);
+          }
+          T aa = a;
+          if (diag && it + c0 + ii == xj[k]) {  // the leave-one-out self pair
+            r2 = T(1);
+            aa = T(0);
+          }
+          T w, f = T(0), lg = T(0);
+          wterms<PM, true, false>(r2, nhp, w, f, lg);
+          const T aw = aa * w;
+          az[k] += aw;
+          const T v = aw * f * (xv[k] - zi);
+          ax[k][0] = fmaT(v, e0, ax[k][0]);
+          ax[k][1] = fmaT(v, e1, ax[k][1]);
+          if constexpr (DIM == 3) ax[k][2] = fmaT(v, e2, ax[k][2]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        two_sum_acc(zh[k], zl[k], az[k]);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) two_sum_acc(xh[k][d], xl[k][d], ax[k][d]);
+      }
+    }
+    if (t + 1 < ntiles) put((t + 1) & 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (xj[k] < n) {
+      const int64_t r = static_cast<int64_t>(blockIdx.y) * n + xj[k];
+      part_z[r] = static_cast<double>(zh[k]) + static_cast<double>(zl[k]);
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+        part_x[r * DIM + d] = static_cast<double>(xh[k][d]) + static_cast<double>(xl[k][d]);
+    }
+  }
+}
+
+// Merges data-coordinate partials in chunk order: dx_j = p s sum_c X_j (s: the sweep's
+// coordinate scale, which converts the scaled sums back to caller units).
+template <typename T, int DIM>
+__global__ __launch_bounds__(kWG) void k_bwd_xmerge(const double* __restrict__ part, int64_t n,
+                                                    int split, double p,
+                                                    const double* __restrict__ hdr,
+                                                    T* __restrict__ grad_x) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
+  if (t >= n * DIM) return;
+  double h = 0.0, l = 0.0;
+  for (int c = 0; c < split; ++c) two_sum_acc(h, l, part[static_cast<int64_t>(c) * n * DIM + t]);
+  grad_x[t] = static_cast<T>(p * hdr[H_SCALE] * (h + l));
+}
+
 // FP64 fix-up of the adjoint for flagged queries (exact hits and near-coincident points),
 // in two passes over the data, each cut into chunks as in k_fwd_fixup:
 //   pass 1: D, Z and the hit count of each flagged query;
@@ -601,14 +771,17 @@ __global__ __launch_bounds__(kWG) void k_bwd_fix2_merge(const int* __restrict__ 
   }
 }
 
-// FP64 dz contributions of the flagged queries, added in ascending query order.
+// FP64 dz and dx contributions of the flagged queries, added in ascending query order
+// (either output may be null).  A query with an exact hit contributes 1/h of its gradient
+// to each coincident point's dz and nothing to dx.
 template <typename T, int DIM, int L, int PM>
 __global__ __launch_bounds__(kWG) void k_bwd_fixz(DevPts data, int64_t n, DevPts query, double p,
                                                   unsigned flags, const int* __restrict__ list,
                                                   const int* __restrict__ count,
                                                   const double* __restrict__ slot_coef,
                                                   const int* __restrict__ slot_hits,
-                                                  T* __restrict__ grad_z) {
+                                                  const double* __restrict__ slot_z,
+                                                  T* __restrict__ grad_z, T* __restrict__ grad_x) {
   const int cnt = *count;
   if (cnt == 0) return;
   const int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
@@ -617,25 +790,36 @@ __global__ __launch_bounds__(kWG) void k_bwd_fixz(DevPts data, int64_t n, DevPts
   const double nhp = -0.5 * p;
   T c[3] = {T(0), T(0), T(0)}, v;
   Loader<T, DIM, L>::data(data, j, c, v);
-  NSum acc;
+  NSum acc, ax[3];
   for (int sl = 0; sl < cnt; ++sl) {
     const int64_t i = list[sl];
     if (excl && i == j) continue;
     T qt[3] = {T(0), T(0), T(0)};
     Loader<T, DIM, L>::query(query, i, qt);
-    double r2 = 0.0;
+    double e[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      const double e = static_cast<double>(qt[d]) - static_cast<double>(c[d]);
-      r2 += e * e;
+      e[d] = static_cast<double>(qt[d]) - static_cast<double>(c[d]);
+      r2 += e[d] * e[d];
     }
     if (slot_hits[sl] > 0) {
       if (r2 == 0.0) acc.add(slot_coef[sl]);
     } else {
-      acc.add(slot_coef[sl] * weight<PM>(r2, nhp));
+      const double w = weight<PM>(r2, nhp);
+      acc.add(slot_coef[sl] * w);
+      if (grad_x) {
+        const double u = p * slot_coef[sl] * (w / r2) * (static_cast<double>(v) - slot_z[sl]);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) ax[d].add(u * e[d]);
+      }
     }
   }
-  grad_z[j] = static_cast<T>(static_cast<double>(grad_z[j]) + acc.value());
+  if (grad_z) grad_z[j] = static_cast<T>(static_cast<double>(grad_z[j]) + acc.value());
+  if (grad_x) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      grad_x[j * DIM + d] = static_cast<T>(static_cast<double>(grad_x[j * DIM + d]) + ax[d].value());
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -728,11 +912,22 @@ hipError_t launch_bwd_fix_t(const BwdArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_bwd_fix2_merge<T, DIM>), dim3(4), dim3(kWG), 0, st, a.list, a.count, a.fix_cmax,
                        a.fpart, a.p, go, gq, a.slot_hits, a.slot_dp, a.slot_den);
   }
-  if (a.grad_z)
+  if (a.grad_z || a.grad_x)
     hipLaunchKernelGGL((k_bwd_fixz<T, DIM, L, PM>),
                        dim3(static_cast<unsigned>((a.n + kWG - 1) / kWG)), dim3(kWG), 0, st,
                        a.data, a.n, a.query, a.p, a.flags, a.list, a.count, a.slot_coef,
-                       a.slot_hits, static_cast<T*>(a.grad_z));
+                       a.slot_hits, a.slot_z, static_cast<T*>(a.grad_z), static_cast<T*>(a.grad_x));
+  return hipGetLastError();
+}
+
+template <typename T, int DIM, int L, int PM>
+hipError_t launch_bwd_datax_t(const BwdArgs& a, int split, int64_t chunk, hipStream_t st) {
+  constexpr int Q = sizeof(T) == 4 ? 4 : 2;
+  const int64_t xpb = static_cast<int64_t>(kWG) * Q;
+  dim3 grid(static_cast<unsigned>((a.n + xpb - 1) / xpb), static_cast<unsigned>(split));
+  hipLaunchKernelGGL((k_bwd_datax<T, DIM, L, PM, Q>), grid, dim3(kWG), 0, st, a.data, a.n, a.query, a.m,
+                     chunk, static_cast<T>(-0.5 * a.p), a.flags, a.hdr, static_cast<const T*>(a.grad_out),
+                     static_cast<const T*>(a.saved_z), a.saved_den, a.part_z, a.part_x);
   return hipGetLastError();
 }
 
@@ -757,6 +952,10 @@ hipError_t bwd_data_pm(const BwdArgs& a, int split, int64_t chunk, double* part,
   IDW_DISPATCH_PM(launch_bwd_data_t, T, DIM, L, a, split, chunk, part, st)
 }
 template <typename T, int DIM, int L>
+hipError_t bwd_datax_pm(const BwdArgs& a, int split, int64_t chunk, hipStream_t st) {
+  IDW_DISPATCH_PM(launch_bwd_datax_t, T, DIM, L, a, split, chunk, st)
+}
+template <typename T, int DIM, int L>
 hipError_t bwd_fix_pm(const BwdArgs& a, hipStream_t st) {
   IDW_DISPATCH_PM(launch_bwd_fix_t, T, DIM, L, a, st)
 }
@@ -775,6 +974,14 @@ hipError_t launch_bwd_zmerge(const BwdArgs& a, int split, const double* part, hi
   dim3 grid(static_cast<unsigned>((a.n + kWG - 1) / kWG));
   hipLaunchKernelGGL((k_bwd_zmerge<T>), grid, dim3(kWG), 0, st, part, a.n, split,
                      static_cast<T*>(a.grad_z));
+  return hipGetLastError();
+}
+
+template <typename T, int DIM>
+hipError_t launch_bwd_xmerge(const BwdArgs& a, int split, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((a.n * DIM + kWG - 1) / kWG));
+  hipLaunchKernelGGL((k_bwd_xmerge<T, DIM>), grid, dim3(kWG), 0, st, a.part_x, a.n, split, a.p, a.hdr,
+                     static_cast<T*>(a.grad_x));
   return hipGetLastError();
 }
 

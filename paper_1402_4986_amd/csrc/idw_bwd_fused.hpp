@@ -1,6 +1,7 @@
 // Fused FP32 adjoint sweep: the query-direction sums (P_i, G_i, for dp and dq) and the
-// data-direction sums (dz_j = sum_i a_i w_ij, a_i = g_i / D_i) from ONE evaluation of
-// each pair's weight.
+// data-direction sums (dz_j = sum_i a_i w_ij, a_i = g_i / D_i, and, for the gradient with
+// respect to the data coordinates, X_j = sum_i a_i (w_ij / r2_ij)(z_j - Z_i)(q_i - x_j))
+// from ONE evaluation of each pair's weight.
 //
 // Lanes own Q queries each (registers).  Data points are staged in LDS in batches of 64,
 // each batch stored twice in a row, so that at step s lane L reads record (L + s) of the
@@ -11,7 +12,8 @@
 // lane L receives the sum held by lane L+1), picking up the contribution of each lane for
 // the same data point.  After 64 steps lane L holds the sum over the wave's 64 x Q
 // queries for batch point (L - 1) mod 64.  That costs one DPP add per lane per step,
-// against a separate data sweep that recomputes every weight.
+// against a separate data sweep that recomputes every weight.  X_j rides the same rotation
+// with one running sum per coordinate.
 //
 // Work decomposition: workgroup (qg, dr) sweeps data range dr for the query blocks
 // qg, qg + G, qg + 2G, ...; it writes the query partials of range dr (as the query sweep
@@ -29,21 +31,29 @@ constexpr int kBatch = 64;                   // data points per rotation batch (
 constexpr int kFTile = 512;                  // data points per LDS tile (8 batches)
 constexpr int kFBatches = kFTile / kBatch;
 
+// Lane L takes the running sum of lane L+1 (wave rotate left by one).
+__device__ __forceinline__ float rotate_in(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+
 // One 64-point batch.  MASK: some pairs must be skipped (padding records beyond the data
 // range, or the leave-one-out self pair); those get r2 = 1 and zero value factors.
-template <int DIM, int PM, int Q, bool NDP, bool NDQ, bool MASK, int UNR>
+// Returns the dz running sum; with NDX, ax holds the X running sums.
+template <int DIM, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool MASK, int UNR>
 __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, int lane, int64_t jb,
                                             int64_t je, bool excl, const float (&qc)[Q][3],
                                             const float (&zq)[Q], const float (&aq)[Q],
                                             const int64_t (&qi)[Q], float nhp, float (&ap)[Q],
-                                            float (&ag)[Q][3]) {
+                                            float (&ag)[Q][3], float (&ax)[3]) {
   float acc = 0.f;
+  ax[0] = ax[1] = ax[2] = 0.f;
   const P4<float>* r0 = rec + lane;
 #pragma unroll UNR
   for (int s = 0; s < kBatch; ++s) {
     const P4<float> d = r0[s];
     const float dv = (DIM == 3) ? d.w : d.z;
     float sz = 0.f;
+    float sx[3] = {0.f, 0.f, 0.f};
     int64_t j = 0;
     bool valid = true;
     if constexpr (MASK) {
@@ -71,21 +81,30 @@ __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, i
         }
       }
       float w, f = 0.f, lg = 0.f;
-      wterms<PM, NDQ, NDP>(r2, nhp, w, f, lg);
+      wterms<PM, NDQ || NDX, NDP>(r2, nhp, w, f, lg);
       const float t = w * c;
       if constexpr (NDP) ap[k] = fmaf(t, lg, ap[k]);
-      if constexpr (NDQ) {
-        const float u = t * f;
-        ag[k][0] = fmaf(u, dx, ag[k][0]);
-        ag[k][1] = fmaf(u, dy, ag[k][1]);
-        if constexpr (DIM == 3) ag[k][2] = fmaf(u, dz, ag[k][2]);
+      if constexpr (NDQ || NDX) {
+        const float u = t * f;  // (w / r2)(z - Z)
+        if constexpr (NDQ) {
+          ag[k][0] = fmaf(u, dx, ag[k][0]);
+          ag[k][1] = fmaf(u, dy, ag[k][1]);
+          if constexpr (DIM == 3) ag[k][2] = fmaf(u, dz, ag[k][2]);
+        }
+        if constexpr (NDX) {
+          const float v = a * u;
+          sx[0] = (k == 0) ? v * dx : fmaf(v, dx, sx[0]);
+          sx[1] = (k == 0) ? v * dy : fmaf(v, dy, sx[1]);
+          if constexpr (DIM == 3) sx[2] = (k == 0) ? v * dz : fmaf(v, dz, sx[2]);
+        }
       }
       sz = (k == 0) ? a * w : fmaf(a, w, sz);
     }
-    // lane L takes the running sum of lane L+1 (wave rotate left by one) and adds its own
-    const float rot = __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, acc), 0x134, 0xF, 0xF, false));
-    acc = rot + sz;
+    acc = rotate_in(acc) + sz;
+    if constexpr (NDX) {
+#pragma unroll
+      for (int e = 0; e < DIM; ++e) ax[e] = rotate_in(ax[e]) + sx[e];
+    }
   }
   return acc;
 }
@@ -95,14 +114,21 @@ __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, i
 // 17.3 with 256-thread workgroups and 512 in the grid.
 constexpr int kFNT = 512;
 
-template <int DIM, int L, int PM, int Q, bool NDP, bool NDQ, int UNR = 2, int WPE = 2, int NT = kFNT>
+// Coordinate given to queries that are left out of a sweep (flagged for the FP64 fix-up):
+// far from every scaled data point, yet with r2 (< 3 * 2^120) and every product of the
+// pair terms finite, so that their zero factors a = 0 give exact zeros.
+constexpr float kFarF = 0x1p60f;
+
+template <int DIM, int L, int PM, int Q, bool NDP, bool NDQ, bool NDX, int UNR = 2, int WPE = 2, int NT = kFNT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_fused(
     DevPts data, int64_t n, DevPts query, int64_t m, int64_t chunk, int groups, float nhp, unsigned flags,
     const double* __restrict__ hdr, const float* __restrict__ saved_z, const float* __restrict__ grad_out,
-    const double* __restrict__ saved_den, double4* __restrict__ part_q, double* __restrict__ part_z) {
+    const double* __restrict__ saved_den, double4* __restrict__ part_q, double* __restrict__ part_z,
+    double* __restrict__ part_x) {
   __shared__ P4<float> tile[2][2 * kFTile];   // batches stored twice in a row
   constexpr int PPT = kFTile / NT;            // tile points staged per thread
   __shared__ float zred[NT / 64][kFTile];    // per-wave dz sums of the current tile
+  __shared__ float xred[NDX ? NT / 64 : 1][NDX ? DIM * kFTile : 1];  // per-wave X sums
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -116,6 +142,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
   const int64_t nqb = (m + qpb - 1) / qpb;
   const int ntiles = static_cast<int>((je - jb + kFTile - 1) / kFTile);
   double* zrow = part_z + static_cast<int64_t>(qg) * n;
+  double* xrow = NDX ? part_x + static_cast<int64_t>(qg) * n * DIM : nullptr;
 
   float rc[PPT][3], rv[PPT];
   auto fetch = [&](int t) {
@@ -160,7 +187,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
         }
       }
 #pragma unroll
-      for (int d = 0; d < 3; ++d) qc[k][d] = ok ? c[d] * s : __builtin_huge_valf();
+      for (int d = 0; d < 3; ++d) qc[k][d] = ok ? c[d] * s : kFarF;
     }
     float ph[Q], pl[Q], gh[Q][3], gl[Q][3];
 #pragma unroll
@@ -188,12 +215,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
         }
         const P4<float>* rec = tile[t & 1] + b * (2 * kBatch);
         const int64_t jbat = jt + b * kBatch;
-        float zs;
+        float zs, ax[3];
         if (diag || tail)
-          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, true, 1>(rec, lane, jbat, je, excl, qc, zq, aq, qi, nhp, ap, ag);
+          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, NDX, true, 1>(rec, lane, jbat, je, excl, qc, zq, aq, qi, nhp,
+                                                             ap, ag, ax);
         else
-          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, false, UNR>(rec, lane, jbat, je, excl, qc, zq, aq, qi, nhp, ap, ag);
-        zred[wave][b * kBatch + ((lane + kBatch - 1) & (kBatch - 1))] = zs;
+          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, NDX, false, UNR>(rec, lane, jbat, je, excl, qc, zq, aq, qi,
+                                                                nhp, ap, ag, ax);
+        const int at = b * kBatch + ((lane + kBatch - 1) & (kBatch - 1));
+        zred[wave][at] = zs;
+        if constexpr (NDX) {
+#pragma unroll
+          for (int e = 0; e < DIM; ++e) xred[wave][e * kFTile + at] = ax[e];
+        }
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
           if constexpr (NDP) two_sum_acc(ph[k], pl[k], ap[k]);
@@ -214,6 +248,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
 #pragma unroll
           for (int w = 1; w < NT / 64; ++w) v += static_cast<double>(zred[w][p]);
           zrow[j] = first ? v : zrow[j] + v;
+          if constexpr (NDX) {
+#pragma unroll
+            for (int e = 0; e < DIM; ++e) {
+              double x = static_cast<double>(xred[0][e * kFTile + p]);
+#pragma unroll
+              for (int w = 1; w < NT / 64; ++w) x += static_cast<double>(xred[w][e * kFTile + p]);
+              xrow[j * DIM + e] = first ? x : xrow[j * DIM + e] + x;
+            }
+          }
         }
       }
       if (t + 1 < ntiles) put((t + 1) & 1);
@@ -233,27 +276,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
   }
   // A group without any query block still owns a partial row: make it zero.
   if (first) {
-    for (int64_t j = jb + tid; j < je; j += NT) zrow[j] = 0.0;
+    for (int64_t j = jb + tid; j < je; j += NT) {
+      zrow[j] = 0.0;
+      if constexpr (NDX) {
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) xrow[j * DIM + e] = 0.0;
+      }
+    }
   }
 }
 
 template <int DIM, int L, int PM>
 hipError_t launch_bwd_fused_t(const BwdArgs& a, int groups, int ranges, int64_t chunk, hipStream_t st) {
-  const bool ndp = (a.flags & 0x4u) != 0, ndq = (a.flags & 0x8u) != 0;
+  const bool ndp = (a.flags & 0x4u) != 0, ndq = (a.flags & 0x8u) != 0, ndx = a.part_x != nullptr;
   dim3 grid(static_cast<unsigned>(groups), static_cast<unsigned>(ranges));
   const float nhp = static_cast<float>(-0.5 * a.p);
   const float* sz = static_cast<const float*>(a.saved_z);
   const float* go = static_cast<const float*>(a.grad_out);
-#define IDW_BF(DP, DQ)                                                                          \
-  hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ>), grid, dim3(kFNT), 0, st, a.data, a.n, \
-                     a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den,     \
-                     a.part_q, a.part_z)
-  if (ndp && ndq)
-    IDW_BF(true, true);
+#define IDW_BF(DP, DQ, DX)                                                                          \
+  hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ, DX>), grid, dim3(kFNT), 0, st, a.data, a.n, \
+                     a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den,         \
+                     a.part_q, a.part_z, a.part_x)
+  // The data-coordinate gradient is instantiated with both query-direction sums (they share
+  // its per-pair factors); merges write only what was requested.
+  if (ndx)
+    IDW_BF(true, true, true);
+  else if (ndp && ndq)
+    IDW_BF(true, true, false);
   else if (ndp)
-    IDW_BF(true, false);
+    IDW_BF(true, false, false);
   else
-    IDW_BF(false, true);
+    IDW_BF(false, true, false);
 #undef IDW_BF
   return hipGetLastError();
 }

@@ -8,13 +8,7 @@
 
 namespace idw {
 
-// Reduces the per-workgroup bounding boxes and fills the workspace header.
-//  extent  = largest side of the data bounding box (1 if zero or not finite);
-//  s       = 2^-e with extent * s in [0.5, 1) for the FP32 sweep (keeps every weight of
-//            points inside the box far from FP32 overflow/underflow; exact scaling), 1 for FP64;
-//  flag thresholds: a query is recomputed in FP64 when its denominator exceeds
-//  (1e-6 * extent)^-p (some data point closer than 1e-6 of the extent, or an exact hit),
-//  or when it is not above the lower threshold (FP32 underflow of the weights).
+// Reduces the per-workgroup extent partials and fills the workspace header.
 __global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ part, int nb,
                                                     int dim, double p, int f32s,
                                                     double* __restrict__ hdr) {
@@ -24,8 +18,8 @@ __global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ p
   for (int d = 0; d < dim; ++d) {
     double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
     for (int b = t; b < nb; b += kWG) {
-      mn = fmin(mn, part[b * 6 + d]);
-      mx = fmax(mx, part[b * 6 + 3 + d]);
+      mn = fmin(mn, part[b * kBboxStride + d]);
+      mx = fmax(mx, part[b * kBboxStride + 3 + d]);
     }
     for (int pass = 0; pass < 2; ++pass) {
       red[t] = pass ? mx : mn;
@@ -42,25 +36,15 @@ __global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ p
     }
     ext = fmax(ext, mx - mn);
   }
-  if (t == 0) {
-    if (!(ext > 0.0) || !(ext < __builtin_huge_val())) ext = 1.0;
-    double s = 1.0;
-    if (f32s) {
-      int e = 0;
-      (void)frexp(ext, &e);
-      s = ldexp(1.0, -e);
-    }
-    const double unit = pow(s, p);
-    const double thr_s = pow(1e-6 * ext * s, -p);
-    const double lo_s = f32s ? ldexp(1.0, -60) : 0.0;
-    hdr[H_SCALE] = s;
-    hdr[H_THR_S] = thr_s;
-    hdr[H_LO_S] = lo_s;
-    hdr[H_DEN_UNIT] = unit;
-    hdr[H_THR_U] = thr_s * unit;
-    hdr[H_LO_U] = lo_s * unit;
-    hdr[H_EXTENT] = ext;
+  double vm = 0.0;
+  for (int b = t; b < nb; b += kWG) vm = fmax(vm, part[b * kBboxStride + 6]);
+  red[t] = vm;
+  __syncthreads();
+  for (int s = kWG / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
   }
+  if (t == 0) fill_header(hdr, ext, red[0], p, f32s != 0);
 }
 
 hipError_t bbox_final(const double* part, int nblocks, int dim, double p, bool f32_scaling,
@@ -222,6 +206,12 @@ hipError_t bwd_qmerge(const BwdArgs& a, bool f64, hipStream_t st) {
                       : launch_bwd_qmerge<double, 2>(a, a.split_q, a.part_q, st);
   return a.dim == 3 ? launch_bwd_qmerge<float, 3>(a, a.split_q, a.part_q, st)
                     : launch_bwd_qmerge<float, 2>(a, a.split_q, a.part_q, st);
+}
+
+hipError_t bwd_xmerge(const BwdArgs& a, int split, bool f64, hipStream_t st) {
+  if (f64)
+    return a.dim == 3 ? launch_bwd_xmerge<double, 3>(a, split, st) : launch_bwd_xmerge<double, 2>(a, split, st);
+  return a.dim == 3 ? launch_bwd_xmerge<float, 3>(a, split, st) : launch_bwd_xmerge<float, 2>(a, split, st);
 }
 
 hipError_t bwd_zmerge(const BwdArgs& a, bool f64, hipStream_t st) {

@@ -228,7 +228,46 @@ enum HdrSlot {
   H_THR_U = 4,     // upper flag threshold, caller units
   H_LO_U = 5,      // lower flag threshold, caller units
   H_EXTENT = 6,    // data extent (largest side of the bounding box; 1 if degenerate)
+  H_VMAX = 7,      // largest |value| of the data points
   H_COUNT_I = 32   // int slots start at byte 256: [0] flagged count
 };
+
+// Per-workgroup partials of the extent kernels: [0..2] coordinate minima, [3..5] maxima,
+// [6] largest |value|, [7] unused.
+constexpr int kBboxStride = 8;
+
+// Fills the header from the data extent and largest |value|.
+//  s = 2^-e with extent * s in [0.5, 1) for the FP32 sweep (exact scaling that keeps every
+//    weight of points inside the box far from FP32 overflow and underflow), 1 for FP64.
+//  A query is recomputed in FP64 when its denominator exceeds (1e-6 * extent)^-p (a data
+//  point closer than 1e-6 of the extent, or an exact hit) or is not above the lower
+//  threshold (FP32 underflow of the weights).  On the FP32 path the upper threshold is also
+//  capped at 2^80 / max(1, max|value|): then every weight is at most 2^80 / max(1, max|value|)
+//  and every distance at least 2^-21 (scaled units), which bounds every FP32 term and sum of
+//  the forward and adjoint sweeps below 2^125.  Thresholds are finite: for large p,
+//  (1e-6 * extent)^-p overflows, and an infinite threshold would pass an infinite denominator.
+__device__ inline void fill_header(double* __restrict__ h, double ext, double vmax, double p,
+                                   bool f32s) {
+  if (!(ext > 0.0) || !(ext < __builtin_huge_val())) ext = 1.0;
+  double s = 1.0;
+  double thr_s = fmin(pow(1e-6 * ext, -p), __DBL_MAX__);
+  double lo_s = 0.0;
+  if (f32s) {
+    int e = 0;
+    (void)frexp(ext, &e);
+    s = ldexp(1.0, -e);
+    thr_s = fmin(pow(1e-6 * ext * s, -p), ldexp(1.0, 80) / fmax(1.0, vmax));
+    lo_s = ldexp(1.0, -60);
+  }
+  const double unit = pow(s, p);
+  h[H_SCALE] = s;
+  h[H_THR_S] = thr_s;
+  h[H_LO_S] = lo_s;
+  h[H_DEN_UNIT] = unit;
+  h[H_THR_U] = fmin(thr_s * unit, __DBL_MAX__);
+  h[H_LO_U] = lo_s * unit;
+  h[H_EXTENT] = ext;
+  h[H_VMAX] = vmax;
+}
 
 }  // namespace idw

@@ -297,12 +297,14 @@ __global__ __launch_bounds__(kWG) void k_fwd_fixmerge(const int* __restrict__ li
   }
 }
 
-// Per-workgroup bounding box of the data coordinates: part[b*6 + d] = min, [+3] = max.
+// Per-workgroup bounding box of the data coordinates and largest |value|, in the
+// kBboxStride-double record of each workgroup.
 template <typename T, int DIM, int L>
 __global__ __launch_bounds__(kWG) void k_bbox(DevPts data, int64_t n, double* __restrict__ part) {
   __shared__ double red[kWG];
   double mn[3] = {__builtin_huge_val(), __builtin_huge_val(), __builtin_huge_val()};
   double mx[3] = {-__builtin_huge_val(), -__builtin_huge_val(), -__builtin_huge_val()};
+  double vm = 0.0;
   for (int64_t j = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; j < n;
        j += static_cast<int64_t>(gridDim.x) * kWG) {
     T c[3] = {T(0), T(0), T(0)}, v;
@@ -312,8 +314,17 @@ __global__ __launch_bounds__(kWG) void k_bbox(DevPts data, int64_t n, double* __
       mn[d] = fmin(mn[d], static_cast<double>(c[d]));
       mx[d] = fmax(mx[d], static_cast<double>(c[d]));
     }
+    vm = fmax(vm, fabs(static_cast<double>(v)));
   }
   const int t = threadIdx.x;
+  red[t] = vm;
+  __syncthreads();
+  for (int s = kWG / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  if (t == 0) part[blockIdx.x * kBboxStride + 6] = red[0];
+  __syncthreads();
   for (int d = 0; d < DIM; ++d) {
     for (int pass = 0; pass < 2; ++pass) {
       red[t] = pass ? mx[d] : mn[d];
@@ -322,7 +333,7 @@ __global__ __launch_bounds__(kWG) void k_bbox(DevPts data, int64_t n, double* __
         if (t < s) red[t] = pass ? fmax(red[t], red[t + s]) : fmin(red[t], red[t + s]);
         __syncthreads();
       }
-      if (t == 0) part[blockIdx.x * 6 + pass * 3 + d] = red[0];
+      if (t == 0) part[blockIdx.x * kBboxStride + pass * 3 + d] = red[0];
       __syncthreads();
     }
   }

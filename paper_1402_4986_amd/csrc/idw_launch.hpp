@@ -50,6 +50,7 @@ struct BwdArgs {
   int64_t chunk_z = 0;
   double4* part_q = nullptr;  // [split_q][m] (P, Gx, Gy, Gz)
   double* part_z = nullptr;   // [split_z][n]
+  double* part_x = nullptr;   // [split_z][n][dim] data-coordinate sums (null: not requested)
   int fused_groups = 0;       // fused FP32 sweep: query-block groups (= dz partial rows)
   int fused_ranges = 0;       // fused FP32 sweep: data ranges (= query partial rows)
   int64_t fused_chunk = 0;
@@ -59,6 +60,7 @@ struct BwdArgs {
   const double* saved_den = nullptr;
   void* grad_z = nullptr;
   void* grad_q = nullptr;
+  void* grad_x = nullptr;
   double* wg_dp = nullptr;      // [num query workgroups] dp partials of the FP32/FP64 sweep
   const int* list = nullptr;    // flagged queries, ascending
   const int* count = nullptr;
@@ -83,6 +85,7 @@ constexpr int kCountBlock = 4096; // flags per compaction block (16 per thread)
                          int nblocks, hipStream_t st);                           \
   hipError_t bwd_query_##NAME(const BwdArgs& a, bool f64, hipStream_t st);       \
   hipError_t bwd_data_##NAME(const BwdArgs& a, bool f64, hipStream_t st);        \
+  hipError_t bwd_datax_##NAME(const BwdArgs& a, bool f64, hipStream_t st);       \
   hipError_t bwd_fixup_##NAME(const BwdArgs& a, bool f64, hipStream_t st);      \
   hipError_t bwd_fused_##NAME(const BwdArgs& a, hipStream_t st);
 
@@ -103,6 +106,7 @@ hipError_t flags_from_den(const double* den, int64_t m, const double* hdr, uint8
                           hipStream_t st);
 hipError_t bwd_qmerge(const BwdArgs& a, bool f64, hipStream_t st);
 hipError_t bwd_zmerge(const BwdArgs& a, bool f64, hipStream_t st);
+hipError_t bwd_xmerge(const BwdArgs& a, int split, bool f64, hipStream_t st);
 hipError_t dp_final(const double* wg_dp, int nwg, const double* slot_dp, const int* count,
                     double* grad_p, hipStream_t st);
 

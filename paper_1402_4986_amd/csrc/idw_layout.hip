@@ -47,6 +47,14 @@ hipError_t IDW_CAT(bwd_data_, IDW_LAYOUT_NAME)(const BwdArgs& a, bool f64, hipSt
                     : bwd_data_pm<float, 2, IDW_LAYOUT>(b, a.split_z, a.chunk_z, a.part_z, st);
 }
 
+hipError_t IDW_CAT(bwd_datax_, IDW_LAYOUT_NAME)(const BwdArgs& a, bool f64, hipStream_t st) {
+  if (f64)
+    return a.dim == 3 ? bwd_datax_pm<double, 3, IDW_LAYOUT>(a, a.split_z, a.chunk_z, st)
+                      : bwd_datax_pm<double, 2, IDW_LAYOUT>(a, a.split_z, a.chunk_z, st);
+  return a.dim == 3 ? bwd_datax_pm<float, 3, IDW_LAYOUT>(a, a.split_z, a.chunk_z, st)
+                    : bwd_datax_pm<float, 2, IDW_LAYOUT>(a, a.split_z, a.chunk_z, st);
+}
+
 hipError_t IDW_CAT(bwd_fixup_, IDW_LAYOUT_NAME)(const BwdArgs& a, bool f64, hipStream_t st) {
   if (f64)
     return a.dim == 3 ? bwd_fix_pm<double, 3, IDW_LAYOUT>(a, st) : bwd_fix_pm<double, 2, IDW_LAYOUT>(a, st);

@@ -132,6 +132,10 @@ def test_workspace_size_grows_with_queries(lib):
         assert lib.idw_workspace_size(ctypes.byref(d), ctypes.byref(q), _lib.FP32, _lib.NEED_DZ, None,
                                       ctypes.byref(f)) == 0
         assert f.value > b.value  # the adjoint needs more than the forward
+        x = ctypes.c_size_t()
+        assert lib.idw_workspace_size(ctypes.byref(d), ctypes.byref(q), _lib.FP32, _lib.NEED_DX, None,
+                                      ctypes.byref(x)) == 0
+        assert x.value > f.value  # the data-coordinate partials come after the rest
         sizes.append(b.value)
     assert sizes[0] < sizes[1] < sizes[2]
 
@@ -140,10 +144,14 @@ def test_backward_argument_checks(lib):
     d = _pts(1000, 2, _lib.HYBRID)
     q = _pts(10, 2, _lib.HYBRID, base=0x20000000)
     args = [ctypes.byref(d), ctypes.byref(q), 2.0, _lib.FP32]
-    rc = lib.idw_backward(*args, 0, 1, 1, 1, None, None, None, 0x4000000, 1 << 30, None, None)
+    rc = lib.idw_backward(*args, 0, 1, 1, 1, None, None, None, None, 0x4000000, 1 << 30, None, None)
     assert rc == _lib.IDW_EINVAL  # no gradient requested
-    rc = lib.idw_backward(*args, _lib.NEED_DZ, 1, 1, 1, None, None, None, 0x4000000, 1 << 30, None, None)
+    rc = lib.idw_backward(*args, _lib.NEED_DZ, 1, 1, 1, None, None, None, None, 0x4000000, 1 << 30, None, None)
     assert rc == _lib.IDW_EINVAL  # grad_z missing
+    rc = lib.idw_backward(*args, _lib.NEED_DX, 1, 1, 1, None, None, None, None, 0x4000000, 1 << 30, None, None)
+    assert rc == _lib.IDW_EINVAL  # grad_x missing
+    rc = lib.idw_backward(*args, 0x20, 1, 1, 1, None, None, None, None, 0x4000000, 1 << 30, None, None)
+    assert rc == _lib.IDW_EINVAL  # unknown flag bit
 
 
 def test_batched_is_declared(lib):

@@ -1,0 +1,107 @@
+"""GPU parity at the edges of the floating-point range: large exponents p and large |values|.
+
+Eq. 1 is scale-free in the weights, but the FP32 sweeps hold raw weights and weighted sums.
+For large p a nearby point's weight (d^-p) exceeds the FP32 range, and for large |z| the
+weighted sums do; then the threshold (1e-6 extent)^-p itself can exceed the FP64 range.
+Such queries must be routed to the FP64 recomputation, in the forward and in the adjoint,
+and agree with the FP64 oracle like any other query.  Every case asserts first that the
+oracle's own result is finite, so that the comparison is meaningful.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import GTOL, TOL, gpu_forward, points, rand_case, scaled_err
+from paper_1402_4986_amd import api, batched, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _backward(x, z, q, p, layout, prec, g):
+    d, qq = points(x, z, q, layout, prec)
+    Z, D = api.forward(d, qq, p, prec)
+    t = torch.float32 if prec == "f32" else torch.float64
+    dz, dp, dq = api.backward(d, qq, p, torch.as_tensor(g, dtype=t, device="cuda"), Z, D, prec)
+    torch.cuda.synchronize()
+    return dz.cpu().numpy().astype(np.float64), float(dp), dq.cpu().numpy().astype(np.float64)
+
+
+# At large p most weight ratios w_ij / D_i are far below FLT_MIN, and so are many dz_j:
+# an FP32 output can only hold such a value to the subnormal spacing 2^-149, which is
+# added to the FP32 bound as an absolute floor (dp is returned in FP64).
+FLOOR = {"f32": 2.0 ** -149, "f64": 0.0}
+
+
+def _check_grad(got, ref, prec):
+    dz, dp, dq = got
+    tol, fl = GTOL[prec], FLOOR[prec]
+    assert np.all(np.isfinite(dz)) and np.isfinite(dp) and np.all(np.isfinite(dq))
+    e = np.abs(dz - ref["dz"]) - tol * ref["dz_scale"]
+    assert np.max(e) <= fl, f"dz err {np.max(e):.3e} above the bound"
+    assert abs(dp - ref["dp"]) <= tol * ref["dp_cond"], f"dp {dp} vs {ref['dp']}"
+    e = np.max(np.abs(dq - ref["dq"]), axis=1) - tol * ref["dq_cond"]
+    assert np.max(e) <= fl, f"dq err {np.max(e):.3e} above the bound"
+
+
+def _case(seed, prec, zscale=1.0):
+    x, z, q = rand_case(seed, 3000, 1000, 2, prec)
+    q[:8] = x[:8]                                   # exact hits
+    t = np.float32 if prec == "f32" else np.float64
+    z = (z * zscale).astype(t).astype(np.float64)
+    g = np.random.default_rng(seed + 1).normal(size=len(q)).astype(t).astype(np.float64)
+    return x, z, q, g
+
+
+# p = 56: (1e-6 extent)^-p is beyond the FP64 range and every FP32 weight of a point
+# closer than about 0.2 of the extent overflows; the FP64 weights of this case stay finite.
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("p", [12.0, 56.0])
+def test_large_exponent_forward_and_adjoint(prec, p):
+    x, z, q, g = _case(61, prec)
+    print(f"case prec={prec} p={p}", flush=True)
+    ref = oracle.forward(x, z, q, p)
+    assert np.all(np.isfinite(ref["Z"])) and np.all(np.isfinite(ref["D"][8:]))
+    for layout in ("aoas", "soa"):
+        Z, _ = gpu_forward(x, z, q, p, layout, prec)
+        assert np.all(np.isfinite(Z))
+        assert np.max(scaled_err(Z, ref)) <= TOL[prec]
+        assert np.array_equal(Z[:8], ref["Z"][:8])
+    gref = oracle.backward(x, z, q, p, g)
+    _check_grad(_backward(x, z, q, p, "hybrid", prec, g), gref, prec)
+
+
+# |z| up to about 3e20 and 3e34: the FP32 weighted sums of a query near a data point
+# exceed the FP32 range unless the query is recomputed in FP64.
+@pytest.mark.parametrize("zscale", [1e20, 1e34])
+@pytest.mark.parametrize("p", [2.0, 3.0])
+def test_large_values_forward_and_adjoint(zscale, p):
+    x, z, q, g = _case(62, "f32", zscale)
+    print(f"case zscale={zscale:g} p={p}", flush=True)
+    ref = oracle.forward(x, z, q, p)
+    assert np.all(np.isfinite(ref["Z"]))
+    Z, _ = gpu_forward(x, z, q, p, "aoas", "f32")
+    assert np.all(np.isfinite(Z))
+    assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
+    gref = oracle.backward(x, z, q, p, g)
+    _check_grad(_backward(x, z, q, p, "aoas", "f32", g), gref, "f32")
+
+
+def test_batched_large_exponent_and_values():
+    # One batch holding an ordinary instance, a p = 56 instance and a |z| ~ 1e34 instance.
+    cases, insts = [], []
+    for k, (p, zs) in enumerate([(2.0, 1.0), (56.0, 1.0), (2.0, 1e34)]):
+        x, z, q, _ = _case(70 + k, "f32", zs)
+        cases.append((x, z, q, p))
+        insts.append(dict(data=torch.tensor(workloads.pack_data(x, z, "aoas", "f32")[0], device="cuda"),
+                          query=torch.tensor(workloads.pack_query(q, "aoas", "f32")[0], device="cuda"),
+                          dim=2, p=p, out_z=torch.empty(len(q), dtype=torch.float32, device="cuda")))
+    plan = batched.BatchedPlan(insts, tuning={})
+    plan.run()
+    torch.cuda.synchronize()
+    for (x, z, q, p), inst in zip(cases, insts):
+        ref = oracle.forward(x, z, q, p)
+        Zg = inst["out_z"].cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(Zg))
+        assert np.max(scaled_err(Zg, ref)) <= TOL["f32"], p
+    plan.close()

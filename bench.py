@@ -81,8 +81,8 @@ def cpu_baseline(x, z, q, g, sample: int, Zgpu, dzgpu_unused=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--layout", default="aoas", choices=["soa", "aos", "aoas", "hybrid", "soaos"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--no-layouts", action="store_true", help="skip the per-layout forward timings")
@@ -114,9 +114,9 @@ def main():
     x, z, q, _ = workloads.plain2d(n, m, "f32", cfg=cfg["cfg"])
     g = np.random.default_rng(7).normal(size=m).astype(np.float32).astype(np.float64)
 
-    def make(layout):
-        d = api.Points.from_arrays(workloads.pack_data(x, z, layout, "f32"), n, 2, layout, dev)
-        qq = api.Points.from_arrays(workloads.pack_query(q, layout, "f32"), m, 2, layout, dev)
+    def make(layout, prec="f32"):
+        d = api.Points.from_arrays(workloads.pack_data(x, z, layout, prec), n, 2, layout, dev)
+        qq = api.Points.from_arrays(workloads.pack_query(q, layout, prec), m, 2, layout, dev)
         return d, qq
 
     data, query = make(args.layout)
@@ -136,11 +136,16 @@ def main():
         step()
     torch.cuda.synchronize()
     _lib.check(lib.idw_timing_enable(1))
+    # events on the launch stream between steps give the per-step durations (median below)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for k in range(args.steps):
         grads = step()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    step_ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps))
     kt = {}
     import ctypes
     for name, which in (("fwd_sweep", _lib.T_FWD_SWEEP), ("bwd_query", _lib.T_BWD_QUERY),
@@ -165,6 +170,7 @@ def main():
     total_flop = sum(FLOP_PER_PAIR[k] for k in kt) * pairs
     out = {"metric": METRIC, "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "median_ms_per_step": round(step_ms[len(step_ms) // 2], 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": "plain2d_f32_1m", "n_data": n, "n_query": m, "dim": 2, "p": p,
@@ -172,6 +178,9 @@ def main():
                       "grads": "dz,dp,dq,dx" if args.need_dx else "dz,dp,dq"},
            "frac_fp32_peak_step": round(total_flop / (ms_step * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
            "kernels": kernels, "roofline": roofline}
+    props = torch.cuda.get_device_properties(dev)
+    out["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", None),
+                     "compute_units": props.multi_processor_count}
 
     if args.calib_copy:
         src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
@@ -183,20 +192,37 @@ def main():
         del src, dst
 
     if not args.no_layouts:
+        # The paper's layout study: the forward of the same 1M x 1M problem in every record
+        # layout, single and double precision (one untimed call, then the mean of two).
         lay = {}
-        for layout in ("soa", "aos", "aoas"):
-            d2, q2 = (data, query) if layout == args.layout else make(layout)
-            api.forward(d2, q2, p, "f32", out_z=Z, out_den=D, ws=ws)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(2):
-                api.forward(d2, q2, p, "f32", out_z=Z, out_den=D, ws=ws)
-            e1.record()
-            torch.cuda.synchronize()
-            lay[layout] = round(e0.elapsed_time(e1) / 2, 3)
-            del d2, q2
+        Z64 = torch.empty(m, dtype=torch.float64, device=dev)
+        for prec in ("f32", "f64"):
+            lay[prec] = {}
+            for layout in ("soa", "aos", "aoas", "hybrid", "soaos"):
+                d2, q2 = (data, query) if (layout == args.layout and prec == "f32") else make(layout, prec)
+                zo = Z if prec == "f32" else Z64
+                api.forward(d2, q2, p, prec, out_z=zo, out_den=D, ws=ws)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(2):
+                    api.forward(d2, q2, p, prec, out_z=zo, out_den=D, ws=ws)
+                e1.record()
+                torch.cuda.synchronize()
+                lay[prec][layout] = round(e0.elapsed_time(e1) / 2, 3)
+                del d2, q2
+        del Z64
         out["forward_ms_by_layout"] = lay
+        # the per-pair Kahan variant of the FP32 forward, same records
+        api.forward(data, query, p, "f32_kahan", out_z=Z, out_den=D, ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
+            api.forward(data, query, p, "f32_kahan", out_z=Z, out_den=D, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        out["forward_ms_f32_kahan"] = round(e0.elapsed_time(e1) / 2, 3)
         api.forward(data, query, p, "f32", out_z=Z, out_den=D, ws=ws)
         torch.cuda.synchronize()
 

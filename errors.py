@@ -55,12 +55,15 @@ def main():
     c = workloads.WORKLOADS["plain2d_f32_1m"]
     x, z, q, _ = workloads.plain2d(c["n"], c["m"], "f32", cfg=c["cfg"])
     Z32, *_ = run(x, z, q, 2.0, "aoas", "f32")
+    Zk, *_ = run(x, z, q, 2.0, "aoas", "f32_kahan")
     Z64, *_ = run(x, z, q, 2.0, "aoas", "f64")
     idx = np.sort(rng.choice(len(q), size=args.sample, replace=False))
     ref = oracle.forward(x, z, q[idx], 2.0)
     out["plain2d_f32_1m"] = {"fp32_vs_oracle": _stats(np.abs(Z32[idx] - ref["Z"]) / ref["S"]),
+                             "fp32_kahan_vs_oracle": _stats(np.abs(Zk[idx] - ref["Z"]) / ref["S"]),
                              "fp64_vs_oracle": _stats(np.abs(Z64[idx] - ref["Z"]) / ref["S"]),
                              "fp32_vs_gpu_fp64_all_queries": _stats(np.abs(Z32 - Z64) / np.maximum(np.abs(Z64), 1e-30)),
+                             "fp32_kahan_vs_gpu_fp64_all_queries": _stats(np.abs(Zk - Z64) / np.maximum(np.abs(Z64), 1e-30)),
                              "queries": f"{args.sample} sampled"}
     print(json.dumps({"plain2d_f32_1m": out["plain2d_f32_1m"]}), flush=True)
 
@@ -69,13 +72,16 @@ def main():
     c = workloads.WORKLOADS["mixture3d_p2.5_262k_1m"]
     x, z, q, hits = workloads.mixture3d(c["n"], c["m"], c["hits"], "f32", cfg=c["cfg"])
     Z32, *_ = run(x, z, q, 2.5, "aoas", "f32")
+    Zk, *_ = run(x, z, q, 2.5, "aoas", "f32_kahan")
     Z64, *_ = run(x, z, q, 2.5, "aoas", "f64")
     idx = np.sort(rng.choice(len(q), size=args.sample, replace=False))
     ref = oracle.forward(x, z, q[idx], 2.5)
     refh = oracle.forward(x, z, q[hits], 2.5)
     out["mixture3d_p2.5_262k_1m"] = {
         "fp32_vs_gpu_fp64_all_queries": _stats(np.abs(Z32 - Z64) / np.maximum(np.abs(Z64), 1e-30)),
+        "fp32_kahan_vs_gpu_fp64_all_queries": _stats(np.abs(Zk - Z64) / np.maximum(np.abs(Z64), 1e-30)),
         "fp32_vs_oracle": _stats(np.abs(Z32[idx] - ref["Z"]) / ref["S"]),
+        "fp32_kahan_vs_oracle": _stats(np.abs(Zk[idx] - ref["Z"]) / ref["S"]),
         "fp64_vs_oracle": _stats(np.abs(Z64[idx] - ref["Z"]) / ref["S"]),
         "exact_hits_bit_exact_fp32": bool(np.all(Z32[hits] == refh["Z"].astype(np.float32))),
         "exact_hits_bit_exact_fp64": bool(np.all(Z64[hits] == refh["Z"])),
@@ -95,10 +101,14 @@ def main():
     eq = np.max(np.abs(dq.cpu().numpy()[idx] - rb["dq"]), axis=1) / rb["dq_cond"]
     ds, qs = d, api.Points.from_arrays(workloads.pack_query(q[idx], "hybrid", "f32"), len(idx), 2, "hybrid", dev)
     Zs, Ds = api.forward(ds, qs, p, "f32")
-    a, b, _ = api.backward(ds, qs, p, torch.tensor(g[idx], dtype=torch.float32, device=dev), Zs, Ds, "f32")
+    a, b, _, dxs = api.backward(ds, qs, p, torch.tensor(g[idx], dtype=torch.float32, device=dev), Zs, Ds, "f32",
+                                need_dx=True)
     torch.cuda.synchronize()
     ez = np.abs(a.cpu().numpy() - rb["dz"]) / rb["dz_scale"]
+    rx = oracle.backward_x(x, z, q[idx], p, g[idx])
+    ex = np.max(np.abs(dxs.cpu().numpy() - rx["dx"]), axis=1) / np.maximum(rx["dx_cond"], 1e-300)
     out["plain2d_grad_f32_128k"] = {"dq_vs_oracle": _stats(eq), "dz_vs_oracle": _stats(ez),
+                                    "dx_vs_oracle": _stats(ex),
                                     "dp_vs_oracle": abs(float(b) - rb["dp"]) / rb["dp_cond"],
                                     "queries": f"{args.sample} sampled"}
     print(json.dumps({"grad": out["plain2d_grad_f32_128k"]}), flush=True)

@@ -66,8 +66,11 @@ enum { IDW_SOA = 0, IDW_AOS = 1, IDW_AOAS = 2, IDW_HYBRID = 3, IDW_SOAOS = 4 };
  *     compensated sums (plain FP32 inside 64-point blocks, TwoSum merge of each block into
  *     hi/lo pairs); the ratio is taken in FP64; queries closer than 1e-6 of the data
  *     extent to a data point (including exact hits) are recomputed entirely in FP64.
- *   IDW_FP64: double inputs/outputs, FP64 sweep with the same blocked compensation. */
-enum { IDW_FP32 = 0, IDW_FP64 = 1 };
+ *   IDW_FP64: double inputs/outputs, FP64 sweep with the same blocked compensation.
+ *   IDW_FP32_KAHAN: as IDW_FP32, but the forward sweep updates its (hi, lo) sums with a
+ *     Kahan step on every pair instead of per block (the accuracy variant; about 1.9x the
+ *     forward's time).  idw_backward treats it as IDW_FP32; batched plans do not take it. */
+enum { IDW_FP32 = 0, IDW_FP64 = 1, IDW_FP32_KAHAN = 2 };
 
 /* Flags. */
 #define IDW_EXCLUDE_SELF 0x1u /* leave-one-out: queries ARE the data set (m == n, same
@@ -88,7 +91,7 @@ typedef struct idw_points {
 
 /* Optional launch configuration; zero fields select the library default.
  *   queries_per_lane  queries held in registers per lane of the forward sweep (FP32: 4 or
- *                     8; FP64: 2 or 4; default 4)
+ *                     8; FP32_KAHAN: 4; FP64: 2 or 4; default 4)
  *   split             number of data chunks swept by separate workgroups and merged in a
  *                     fixed order (1..1024); 0 = chosen from m so the chip is filled
  *   batch_chunk       batched plans: data points per work item (rounded up to 512;

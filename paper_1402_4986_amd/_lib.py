@@ -12,11 +12,11 @@ LIB_PATH = os.path.join(_HERE, "libidw.so")
 
 IDW_OK, IDW_EINVAL, IDW_EDEVICE, IDW_ENOMEM, IDW_EUNSUPPORTED, IDW_EWORKSPACE = range(6)
 SOA, AOS, AOAS, HYBRID, SOAOS = range(5)
-FP32, FP64 = 0, 1
+FP32, FP64, FP32_KAHAN = 0, 1, 2
 EXCLUDE_SELF, NEED_DZ, NEED_DP, NEED_DQ, NEED_DX = 0x1, 0x2, 0x4, 0x8, 0x10
 
 LAYOUT_CODES = {"soa": SOA, "aos": AOS, "aoas": AOAS, "hybrid": HYBRID, "soaos": SOAOS}
-PRECISION_CODES = {"f32": FP32, "f64": FP64}
+PRECISION_CODES = {"f32": FP32, "f64": FP64, "f32_kahan": FP32_KAHAN}
 
 EXPORTED = ("idw_version", "idw_last_error", "idw_record_bytes", "idw_workspace_size",
             "idw_forward", "idw_backward", "idw_timing_enable", "idw_timing_read", "idw_batched_plan_create",

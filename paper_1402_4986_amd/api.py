@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import IdwConfig, IdwPoints, check
 
-_TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64}
+_TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64, "f32_kahan": torch.float32}
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:

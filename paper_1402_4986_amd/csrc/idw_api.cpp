@@ -59,11 +59,12 @@ int check_device() {
 
 // ---- validation ----
 static size_t elem(int precision) { return precision == IDW_FP64 ? 8 : 4; }
+static bool known_precision(int p) { return p == IDW_FP32 || p == IDW_FP64 || p == IDW_FP32_KAHAN; }
 
 int record_bytes(int layout, int dim, int precision, bool is_data, size_t b[4]) {
   for (int k = 0; k < 4; ++k) b[k] = 0;
   if (dim != 2 && dim != 3) return fail(IDW_EINVAL, "dim must be 2 or 3 (got %d)", dim);
-  if (precision != IDW_FP32 && precision != IDW_FP64)
+  if (!known_precision(precision))
     return fail(IDW_EINVAL, "unknown precision %d", precision);
   const size_t e = elem(precision);
   switch (layout) {
@@ -126,7 +127,7 @@ static bool same_query_layout(int a, int b) {
 
 int validate_common(const idw_points* data, const idw_points* query, double p, int precision,
                     uint32_t flags) {
-  if (precision != IDW_FP32 && precision != IDW_FP64)
+  if (!known_precision(precision))
     return fail(IDW_EINVAL, "unknown precision %d", precision);
   int rc = validate_points(data, precision, true, "data");
   if (rc) return rc;
@@ -384,7 +385,7 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   if (flags & ~IDW_EXCLUDE_SELF) return fail(IDW_EINVAL, "idw_forward accepts only IDW_EXCLUDE_SELF");
   if (cfg && cfg->queries_per_lane) {
     const int q = cfg->queries_per_lane;
-    const bool ok = precision == IDW_FP64 ? (q == 2 || q == 4) : (q == 4 || q == 8);
+    const bool ok = precision == IDW_FP64 ? (q == 2 || q == 4) : precision == IDW_FP32_KAHAN ? q == 4 : (q == 4 || q == 8);
     if (!ok) return fail(IDW_EUNSUPPORTED, "queries_per_lane %d not built for this precision", q);
   }
   if (cfg && (cfg->split < 0 || cfg->split > 1024)) return fail(IDW_EINVAL, "split must be in 0..1024");
@@ -410,6 +411,7 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   a.p = p;
   a.flags = flags;
   a.q_per_lane = w.qf;
+  a.kahan = precision == IDW_FP32_KAHAN;
   a.split = w.split_f;
   a.chunk = w.chunk_f;
   a.hdr = reinterpret_cast<const double*>(ws + w.hdr);

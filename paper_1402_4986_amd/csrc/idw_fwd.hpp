@@ -60,12 +60,43 @@ __device__ __forceinline__ P4<T> stage(const T (&c)[3], T v, T s) {
   return r;
 }
 
+// Kahan step: adds x to the pair (s, e), e carrying the rounding error lost so far
+// (s + e is the compensated sum).
+template <typename T>
+__device__ __forceinline__ void kahan_add(T& s, T& e, T x) {
+  const T y = x + e;
+  const T t = s + y;
+  e = y - (t - s);
+  s = t;
+}
+
 // Consume one LDS tile: for each of the lane's Q queries, accumulate w*z and w.
-template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR>
+// KH = false: plain sums over 64-record blocks, each merged into (hi, lo) by TwoSum.
+// KH = true: Kahan-compensated update of (hi, lo) on every pair (about 3 more VALU
+// operations per accumulator and pair; the accuracy variant).
+template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR, bool KH = false>
 __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t jt,
                                          const T (&qc)[Q][3], const int64_t (&qi)[Q], T nhp,
                                          T (&nh)[Q], T (&nl)[Q], T (&dh)[Q], T (&dl)[Q]) {
   constexpr int CH = 64;
+  if constexpr (KH) {
+#pragma unroll UNR
+    for (int jj = 0; jj < kTile; ++jj) {
+      const P4<T> d = tl[jj];
+      const T dv = (DIM == 3) ? d.w : d.z;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        const T r2 = sqdist<T, DIM>(qc[k], d);
+        T w = weight<PM>(r2, nhp);
+        if constexpr (DIAG) {
+          if (jt + jj == qi[k]) w = T(0);
+        }
+        kahan_add(nh[k], nl[k], w * dv);
+        kahan_add(dh[k], dl[k], w);
+      }
+    }
+    return;
+  }
   for (int c0 = 0; c0 < kTile; c0 += CH) {
     T an[Q], ad[Q];
 #pragma unroll
@@ -118,7 +149,7 @@ struct SweepTune {
 };
 
 template <typename T, int DIM, int L, int PM, int Q, int UNR = SweepTune<T, Q>::UNR,
-          int WPE = SweepTune<T, Q>::WPE>
+          int WPE = SweepTune<T, Q>::WPE, bool KH = false>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_fwd_sweep(DevPts data, int64_t n, DevPts query, int64_t m,
                                                    int64_t chunk, int split, T nhp, unsigned flags,
                                                    const double* __restrict__ hdr,
@@ -175,9 +206,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
     const int64_t jt = jb + static_cast<int64_t>(t) * kTile;
     const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
     if (diag)
-      fwd_tile<T, DIM, PM, Q, true, 1>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
+      fwd_tile<T, DIM, PM, Q, true, 1, KH>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
     else
-      fwd_tile<T, DIM, PM, Q, false, UNR>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
+      fwd_tile<T, DIM, PM, Q, false, UNR, KH>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }
@@ -356,6 +387,13 @@ hipError_t launch_fwd_sweep_q(const FwdArgs& a, hipStream_t st) {
                        a.out_den, a.flag, a.part);                                          \
     break;
   if constexpr (sizeof(T) == 4) {
+    if (a.kahan) {  // per-pair Kahan variant, 4 queries per lane
+      if (Q != 4) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, SweepTune<T, 4>::UNR, SweepTune<T, 4>::WPE, true>), grid,
+                         dim3(kWG), 0, st, a.data, a.n, a.query, a.m, a.chunk, a.split, nhp, a.flags, a.hdr, z,
+                         a.out_den, a.flag, a.part);
+      return hipGetLastError();
+    }
     switch (Q) {
       IDW_FWD_Q(4)
       IDW_FWD_Q(8)

@@ -19,6 +19,7 @@ struct FwdArgs {
   double p = 2.0;
   unsigned flags = 0;
   int q_per_lane = 8;
+  bool kahan = false;  // FP32 sweep with per-pair Kahan compensation
   int split = 1;
   int64_t chunk = 0;  // data points per split chunk (multiple of the tile)
   const double* hdr = nullptr;

@@ -42,7 +42,7 @@ def rng_for(cfg: int, stream: int = 0) -> np.random.Generator:
 
 
 def _round(a: np.ndarray, dtype: str) -> np.ndarray:
-    if dtype == "f32":
+    if dtype != "f64":  # "f32" and "f32_kahan"
         return a.astype(np.float32).astype(np.float64)
     return a.astype(np.float64)
 
@@ -118,7 +118,7 @@ def batched(count: int = 64, nlo: int = 1024, nhi: int = 262144, mlo: int = 1024
 # ----------------------------------------------------------------------------------------
 
 def _np_dtype(dtype: str):
-    return np.float32 if dtype == "f32" else np.float64
+    return np.float64 if dtype == "f64" else np.float32  # "f32" and "f32_kahan"
 
 
 def pack_data(x: np.ndarray, z: np.ndarray, layout: str, dtype: str):

@@ -8,7 +8,7 @@ import torch
 import oracle
 from paper_1402_4986_amd import api, workloads
 
-TOL = {"f32": 1e-5, "f64": 1e-12}       # scale-aware relative error of Z (forward)
+TOL = {"f32": 1e-5, "f32_kahan": 1e-5, "f64": 1e-12}  # scale-aware relative error of Z
 GTOL = {"f32": 1e-5, "f64": 1e-12}      # condition-aware relative error of the gradients
 
 
@@ -38,5 +38,5 @@ def rand_case(seed, n, m, dim, prec="f32", lo=0.0, hi=1.0):
     x = r.uniform(lo, hi, (n, dim))
     z = np.sin(3 * x[:, 0]) + np.cos(2 * x[:, 1]) + r.normal(0, 0.1, n)
     q = r.uniform(lo, hi, (m, dim))
-    t = np.float32 if prec == "f32" else np.float64
+    t = np.float64 if prec == "f64" else np.float32
     return x.astype(t).astype(np.float64), z.astype(t).astype(np.float64), q.astype(t).astype(np.float64)

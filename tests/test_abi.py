@@ -190,3 +190,24 @@ def test_batched_plan_argument_checks(lib):
     rc = lib.idw_batched_plan_create(arr, 2, _lib.FP32, None, ctypes.byref(plan))
     assert rc == _lib.IDW_EINVAL and b"instance 0" in lib.idw_last_error()
     assert not plan.value
+
+
+def test_kahan_precision_is_fp32_storage_with_its_own_limits(lib):
+    # IDW_FP32_KAHAN stores FP32 records, builds only 4 queries per lane, and batched
+    # plans do not take it.
+    for layout in (_lib.SOA, _lib.AOS, _lib.AOAS, _lib.HYBRID, _lib.SOAOS):
+        assert _rb(lib, layout, 3, _lib.FP32_KAHAN, 1) == _rb(lib, layout, 3, _lib.FP32, 1)
+    d = _pts(1000, 2, _lib.AOAS)
+    q = _pts(500, 2, _lib.AOAS, base=0x20000000)
+    cfg = _lib.IdwConfig()
+    cfg.queries_per_lane = 8
+    rc = lib.idw_forward(ctypes.byref(d), ctypes.byref(q), 2.0, _lib.FP32_KAHAN, 0, 0x8000000, None, 0x4000000,
+                         1 << 30, None, ctypes.byref(cfg))
+    assert rc == _lib.IDW_EUNSUPPORTED
+    plan = ctypes.c_void_p()
+    arr = (_lib.IdwInstance * 1)()
+    arr[0].data = d
+    arr[0].query = q
+    arr[0].p = 2.0
+    arr[0].out_z = 0x30000000
+    assert lib.idw_batched_plan_create(arr, 1, _lib.FP32_KAHAN, None, ctypes.byref(plan)) == _lib.IDW_EUNSUPPORTED

@@ -68,11 +68,20 @@ __device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& f, 
 template <int PM, bool NDQ, bool NDP>
 __device__ __forceinline__ void wterms(double r2, double nhp, double& w, double& f, double& lg) {
   if constexpr (NDP || PM == PM_GEN) lg = log2(r2);
-  if constexpr (PM == PM_GEN)
+  if constexpr (PM == PM_GEN) {
     w = exp2(nhp * lg);
-  else
+    if constexpr (NDQ) f = rcp64(r2);
+  } else if constexpr (PM == PM_2) {
+    w = rcp64(r2);
+    if constexpr (NDQ) f = w;
+  } else if constexpr (PM == PM_4) {
+    const double t = rcp64(r2);
+    w = t * t;
+    if constexpr (NDQ) f = t;
+  } else {
     w = weight<PM>(r2, nhp);
-  if constexpr (NDQ) f = 1.0 / r2;
+    if constexpr (NDQ) f = rcp64(r2);
+  }
 }
 
 // One LDS tile of the query sweep.  `cnt` records are valid (all of them unless TAIL).

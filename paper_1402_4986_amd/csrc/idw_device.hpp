@@ -126,17 +126,31 @@ __device__ __forceinline__ float weight(float r2, float nhp) {
   }
 }
 
+// 1/a in FP64: the hardware reciprocal estimate refined by two Newton steps (each about
+// squares the relative error), then the division fix-up instruction, which returns the
+// IEEE result for a = 0, +-inf and NaN (where the Newton steps would give NaN).  Within
+// about 1 ulp of the correctly rounded quotient, in 6 instructions against about 10 for
+// the IEEE division sequence.
+__device__ __forceinline__ double rcp64(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-a, y, 1.0);
+  y = fma(y, e, y);
+  return __builtin_amdgcn_div_fixup(y, a, 1.0);
+}
+
 template <int PM>
 __device__ __forceinline__ double weight(double r2, double nhp) {
   if constexpr (PM == PM_2) {
-    return 1.0 / r2;
+    return rcp64(r2);
   } else if constexpr (PM == PM_1) {
     return 1.0 / sqrt(r2);
   } else if constexpr (PM == PM_3) {
     const double s = 1.0 / sqrt(r2);
     return s * s * s;
   } else if constexpr (PM == PM_4) {
-    const double t = 1.0 / r2;
+    const double t = rcp64(r2);
     return t * t;
   } else if constexpr (PM == PM_25) {
     const double s = 1.0 / sqrt(r2);

@@ -78,6 +78,49 @@ def cpu_baseline(x, z, q, g, sample: int, Zgpu, dzgpu_unused=None):
     return rec, idx, ref
 
 
+_SLICE_INPUTS = {}
+
+
+def _oracle_slice(idx):
+    import oracle
+    d = _SLICE_INPUTS
+    oracle.forward(d["x"], d["z"], d["q"][idx], 2.0)
+    oracle.backward(d["x"], d["z"], d["q"][idx], 2.0, d["g"][idx])
+    return len(idx)
+
+
+def cpu_baseline_all_cores(x, z, q, g, per_proc: int):
+    """Times the same oracle on every usable host core (at most 16): one forked process per
+    slice of seeded queries, each against all n data points.  Called before anything
+    touches the GPU, so the workers inherit no device state."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    nproc = max(1, min(16, len(os.sched_getaffinity(0))))
+    idx = np.sort(np.random.default_rng(98).choice(len(q), size=nproc * per_proc, replace=False))
+    _SLICE_INPUTS.update(x=x, z=z, q=q, g=g)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(nproc) as pool:
+        pool.map(_oracle_slice, np.array_split(idx, nproc))
+    dt = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    pairs = float(len(idx)) * len(x)
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": nproc, "kind": "oracle",
+            "cpu": model,
+            "sample": f"{len(idx)} seeded queries x all {len(x)} data points, forward + adjoint "
+                      f"(dz, dp, dq), FP64, {nproc} processes, {dt:.1f} s wall"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +130,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--no-layouts", action="store_true", help="skip the per-layout forward timings")
     ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--cpu-sample-per-core", type=int, default=24)
     ap.add_argument("--separate-adjoint", action="store_true",
                     help="run the adjoint as separate query- and data-direction sweeps")
     ap.add_argument("--need-dx", action="store_true",
@@ -95,8 +139,8 @@ def main():
                     help="also run one device-to-device copy of 512 MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the sweep is measured on one GPU's share "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the sweep is measured on one GPU's share of "
+              "the work; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -104,15 +148,19 @@ def main():
 
     from paper_1402_4986_amd import _lib, api, workloads
 
+    cfg = workloads.WORKLOADS["plain2d_f32_1m"]
+    n, m, p = cfg["n"], cfg["m"], cfg["p"]
+    x, z, q, _ = workloads.plain2d(n, m, "f32", cfg=cfg["cfg"])
+    g = np.random.default_rng(7).normal(size=m).astype(np.float32).astype(np.float64)
+    all_cores = None
+    if not args.no_cpu:  # before the GPU is initialised (the workers are forked)
+        all_cores = cpu_baseline_all_cores(x, z, q, g, args.cpu_sample_per_core)
+
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     lib = _lib.load()
     dev = torch.device("cuda:0")
-    cfg = workloads.WORKLOADS["plain2d_f32_1m"]
-    n, m, p = cfg["n"], cfg["m"], cfg["p"]
-    x, z, q, _ = workloads.plain2d(n, m, "f32", cfg=cfg["cfg"])
-    g = np.random.default_rng(7).normal(size=m).astype(np.float32).astype(np.float64)
 
     def make(layout, prec="f32"):
         d = api.Points.from_arrays(workloads.pack_data(x, z, layout, prec), n, 2, layout, dev)
@@ -230,6 +278,7 @@ def main():
         Zh = Z.cpu().numpy().astype(np.float64)
         rec, idx, ref = cpu_baseline(x, z, q, g, args.cpu_sample, Zh)
         out["cpu_baseline"] = rec
+        out["cpu_baseline_all_cores"] = all_cores
         err = np.abs(Zh[idx] - ref["Z"]) / ref["S"]
         out["err_vs_fp64"] = {"max": float(err.max()), "median": float(np.median(err)),
                               "metric": "|Z - Z_oracle| / (sum w|z| / sum w)",

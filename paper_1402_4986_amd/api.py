@@ -85,8 +85,9 @@ _ws_cache: dict = {}
 def workspace(data: Points, query: Points, precision: str, cfg: Optional[IdwConfig] = None,
               backward: bool = True, need_dx: bool = False) -> torch.Tensor:
     """A device workspace for the forward (backward=False) or for forward and backward on
-    these point sets, with room for the data-coordinate gradient when need_dx (cached per
-    device and grown on demand)."""
+    these point sets, with room for the data-coordinate gradient when need_dx.  Cached per
+    (device, current stream) and grown on demand: calls enqueued on one stream run in order,
+    so they may share it, while work on another stream gets its own."""
     lib = _lib.load()
     need = ctypes.c_size_t()
     dc, qc = data.c(), query.c()
@@ -95,7 +96,7 @@ def workspace(data: Points, query: Points, precision: str, cfg: Optional[IdwConf
         flags |= _lib.NEED_DX
     check(lib.idw_workspace_size(ctypes.byref(dc), ctypes.byref(qc), _lib.PRECISION_CODES[precision], flags,
                                  ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(need)))
-    key = (str(data.device),)
+    key = (str(data.device), _stream_handle(data.device))
     ws = _ws_cache.get(key)
     if ws is None or ws.numel() < need.value:
         ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device=data.device)

@@ -295,11 +295,13 @@ hipError_t timed(int which, hipStream_t st, F&& launch) {
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
   if (e == hipSuccess) e = hipEventRecord(a, st);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(b, st);
-  if (e != hipSuccess) return e;
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, st);
+  if (e != hipSuccess) {  // nothing is queued on the events: release them
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    return e;
+  }
   std::lock_guard<std::mutex> lk(g_tmu);
   g_pending.push_back({which, a, b});
   return hipSuccess;

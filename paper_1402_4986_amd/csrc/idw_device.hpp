@@ -161,23 +161,6 @@ __device__ __forceinline__ double weight(double r2, double nhp) {
   }
 }
 
-// w / r2 given w (for the query-position gradient), in the same arithmetic.
-template <int PM>
-__device__ __forceinline__ float weight_over_r2(float w, float r2) {
-  if constexpr (PM == PM_2) {
-    return w * w;  // w = 1/r2
-  } else if constexpr (PM == PM_4) {
-    return w * __builtin_amdgcn_sqrtf(w);  // w = r2^-2 -> r2^-3 = w^1.5
-  } else {
-    return w * __builtin_amdgcn_rcpf(r2);
-  }
-}
-
-template <int PM>
-__device__ __forceinline__ double weight_over_r2(double w, double r2) {
-  return w / r2;
-}
-
 // ---------------------------------------------------------------------------------------
 // Compensated accumulation: (hi, lo) += x with Knuth's TwoSum (no magnitude assumption).
 // ---------------------------------------------------------------------------------------

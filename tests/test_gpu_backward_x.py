@@ -148,3 +148,18 @@ def test_gradcheck_fp64_with_data_coordinates():
     p = torch.tensor(1.8, dtype=torch.float64, device="cuda", requires_grad=True)
     assert torch.autograd.gradcheck(lambda a, b, c, d: api.interpolate(a, b, c, d), (X, V, Q, p),
                                     eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_dx_degenerate_sizes():
+    # No queries: every gradient is zero.  One data point: Z is that point's value for every
+    # query, so its position has no gradient.
+    x, z, q = rand_case(490, 500, 0, 2)
+    d, qq = points(x, z, np.zeros((0, 2)), "aoas", "f32")
+    dz, dp, dq, dx = api.backward(d, qq, 2.0, torch.zeros(0, device="cuda"), torch.zeros(0, device="cuda"),
+                                  torch.zeros(0, dtype=torch.float64, device="cuda"), "f32", need_dx=True)
+    torch.cuda.synchronize()
+    assert torch.all(dz == 0) and float(dp) == 0.0 and torch.all(dx == 0) and dq.numel() == 0
+    x1, z1, q1 = rand_case(491, 1, 300, 3)
+    g = _g(15, 300, "f32")
+    _, _, _, dx1 = _run(x1, z1, q1, 2.0, "hybrid", "f32", g)
+    assert np.all(dx1 == 0.0)

@@ -14,9 +14,10 @@ def pytest_configure(config):
 
 
 def _gpu_available():
+    # device_count() does not initialise the GPU in this process (is_available() would).
     try:
         import torch
-        return torch.cuda.is_available()
+        return torch.cuda.device_count() > 0
     except Exception:
         return False
 

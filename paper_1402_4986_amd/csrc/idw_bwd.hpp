@@ -67,7 +67,7 @@ __device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& f, 
 
 template <int PM, bool NDQ, bool NDP>
 __device__ __forceinline__ void wterms(double r2, double nhp, double& w, double& f, double& lg) {
-  if constexpr (NDP || PM == PM_GEN) lg = log2(r2);
+  if constexpr (NDP || PM == PM_GEN) lg = log2_64(r2);
   if constexpr (PM == PM_GEN) {
     w = exp2(nhp * lg);
     if constexpr (NDQ) f = rcp64(r2);

@@ -141,23 +141,69 @@ __device__ __forceinline__ double rcp64(double a) {
   return __builtin_amdgcn_div_fixup(y, a, 1.0);
 }
 
+// 1/sqrt(a) in FP64: the hardware estimate refined by two Newton steps; for a = 0, inf and
+// NaN the estimate itself (inf, 0, NaN) is returned.  Within 1.0 ulp on MI355X over 2^21
+// log-uniform a in [2^-60, 2^60] (about 8 instructions against about 20 for a correctly
+// rounded square root and division).
+__device__ __forceinline__ double rsq64(double a) {
+  const double y0 = __builtin_amdgcn_rsq(a);
+  double y = y0;
+  double t = a * y;
+  double e = fma(-t, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  t = a * y;
+  e = fma(-t, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  return (a > 0.0 && a < __builtin_huge_val()) ? y : y0;
+}
+
+// log2(a) in FP64 for the weights and the power gradient: a = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 0.172, summed
+// as 2 s (1 + s^2/3 + ... + s^20/21) (truncation below 2^-60); log2 a = e + ln m / ln 2.
+// log2(0) = -inf, log2(inf) = inf, NaN passes through.  Within 4.1 ulp on MI355X over 2^21
+// inputs (log-uniform in [2^-60, 2^60], a quarter within 1e-3 of 1), in about 33
+// instructions against about 70 for the library's correctly rounded form.
+__device__ __forceinline__ double log2_64(double a) {
+  double m = __builtin_amdgcn_frexp_mant(a);
+  int e = __builtin_amdgcn_frexp_exp(a);
+  const bool low = m < 0.70710678118654752440;
+  m = low ? m + m : m;
+  e = low ? e - 1 : e;
+  const double s = (m - 1.0) * rcp64(m + 1.0);
+  const double z = s * s;
+  double p = 1.0 / 21.0;
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  p = fma(p, z, 1.0);
+  const double r = fma((s + s) * p, 1.44269504088896340736, static_cast<double>(e));
+  if (a > 0.0 && a < __builtin_huge_val()) return r;
+  return a == 0.0 ? -__builtin_huge_val() : a;
+}
+
 template <int PM>
 __device__ __forceinline__ double weight(double r2, double nhp) {
   if constexpr (PM == PM_2) {
     return rcp64(r2);
   } else if constexpr (PM == PM_1) {
-    return 1.0 / sqrt(r2);
+    return rsq64(r2);
   } else if constexpr (PM == PM_3) {
-    const double s = 1.0 / sqrt(r2);
+    const double s = rsq64(r2);
     return s * s * s;
   } else if constexpr (PM == PM_4) {
     const double t = rcp64(r2);
     return t * t;
   } else if constexpr (PM == PM_25) {
-    const double s = 1.0 / sqrt(r2);
+    const double s = rsq64(r2);
     return s * s * sqrt(s);
   } else {
-    return exp2(nhp * log2(r2));
+    return exp2(nhp * log2_64(r2));
   }
 }
 

@@ -212,6 +212,7 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   w.flag = take(static_cast<size_t>(m));
   w.bcnt = take(sizeof(int) * static_cast<size_t>(nb + 1));
   w.list = take(sizeof(int) * static_cast<size_t>(m));
+  w.near_min = take(sizeof(unsigned long long) * static_cast<size_t>(m));
   w.part_f = take(w.split_f > 1 ? sizeof(double2) * static_cast<size_t>(w.split_f) * m : 0);
   w.fpart = take(sizeof(double4) * kFixGrid);
   w.fix_cmax = static_cast<int>(std::min<int64_t>(kFixGrid, std::max<int64_t>(1, cdiv(n, 4096))));
@@ -241,11 +242,12 @@ struct LayoutFns {
   hipError_t (*bwd_datax)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_fixup)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_fused)(const BwdArgs&, hipStream_t);
+  hipError_t (*near_check)(const NearArgs&, hipStream_t);
 };
 
 #define IDW_FNS(NAME)                                                                   \
   {fwd_sweep_##NAME, fwd_fixup_##NAME, bbox_##NAME,      bwd_query_##NAME, bwd_data_##NAME, \
-   bwd_datax_##NAME, bwd_fixup_##NAME, bwd_fused_##NAME}
+   bwd_datax_##NAME, bwd_fixup_##NAME, bwd_fused_##NAME, near_check_##NAME}
 static const LayoutFns kFns[5] = {IDW_FNS(soa), IDW_FNS(aos), IDW_FNS(aoas), IDW_FNS(hybrid), IDW_FNS(soaos)};
 #undef IDW_FNS
 
@@ -272,6 +274,35 @@ hipError_t enqueue_header(const idw_points* data, double p, bool f64, char* ws, 
   if (e != hipSuccess) return e;
   return bbox_final(reinterpret_cast<double*>(ws + w.bbox), w.nbbox, data->dim, p, !f64,
                     reinterpret_cast<double*>(ws + w.hdr), st);
+}
+
+// Settles the route of every query after a sweep (or from the saved denominators): the
+// candidates are compacted and checked for a data point within 1e-6 of the extent, then the
+// queries routed to FP64 are compacted into the list the fix-ups read.
+static hipError_t settle_routes(const LayoutFns& F, const idw_points* data, const idw_points* query,
+                                bool f64, bool excl, char* ws, const WsPlan& w, hipStream_t st) {
+  uint8_t* route = reinterpret_cast<uint8_t*>(ws + w.flag);
+  int* bcnt = reinterpret_cast<int*>(ws + w.bcnt);
+  int* list = reinterpret_cast<int*>(ws + w.list);
+  int* count = reinterpret_cast<int*>(ws + w.hdr + 256);
+  const int64_t m = query->n;
+  hipError_t e = compact_flags(route, m, bcnt, list, count, F_CANDIDATE, st);
+  if (e != hipSuccess) return e;
+  NearArgs na;
+  na.data = dev_pts(data);
+  na.n = data->n;
+  na.query = dev_pts(query);
+  na.m = m;
+  na.dim = data->dim;
+  na.f64 = f64;
+  na.excl = excl;
+  na.list = list;
+  na.count = count;
+  na.hdr = reinterpret_cast<const double*>(ws + w.hdr);
+  na.route = route;
+  na.minb = reinterpret_cast<unsigned long long*>(ws + w.near_min);
+  if ((e = F.near_check(na, st)) != hipSuccess) return e;
+  return compact_flags(route, m, bcnt, list, count, F_FP64, st);
 }
 
 // ---- optional event timing of the sweep kernels ----
@@ -433,10 +464,8 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   if (a.split > 1 &&
       (rc = check_hip(merge_split(a.part, m, a.split, a.hdr, out_z, f64, out_den, a.flag, st), "merge")))
     return rc;
-  if ((rc = check_hip(compact_flags(a.flag, m, reinterpret_cast<int*>(ws + w.bcnt),
-                                    reinterpret_cast<int*>(ws + w.list),
-                                    reinterpret_cast<int*>(ws + w.hdr + 256), st),
-                      "compaction")))
+  if ((rc = check_hip(settle_routes(F, data, query, f64, (flags & IDW_EXCLUDE_SELF) != 0, ws, w, st),
+                      "near-coincidence check")))
     return rc;
   if ((rc = check_hip(F.fwd_fixup(a, f64, st), "FP64 fix-up"))) return rc;
   return IDW_OK;
@@ -518,11 +547,10 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
   uint8_t* flag = reinterpret_cast<uint8_t*>(ws + w.flag);
   if ((rc = check_hip(enqueue_header(data, p, f64, ws, w, st), "extent kernels"))) return rc;
   if ((rc = check_hip(flags_from_den(saved_den, m, a.hdr, flag, st), "flags"))) return rc;
-  if ((rc = check_hip(compact_flags(flag, m, reinterpret_cast<int*>(ws + w.bcnt),
-                                    reinterpret_cast<int*>(ws + w.list),
-                                    reinterpret_cast<int*>(ws + w.hdr + 256), st),
-                      "compaction")))
+  if ((rc = check_hip(settle_routes(F, data, query, f64, (flags & IDW_EXCLUDE_SELF) != 0, ws, w, st),
+                      "near-coincidence check")))
     return rc;
+  a.route = flag;
   // The fused FP32 sweep pays off when both directions are needed: dz or dx with dp or dq,
   // or dx alone (its per-pair factors are those of dq).
   const bool fused = !f64 && (ndx || (ndz && (ndp || ndq))) && w.fused_groups > 0 &&

@@ -21,7 +21,7 @@ struct WsPlan {
   int nbbox = 1, nwg_dp = 1;
   int fused_groups = 0, fused_ranges = 0;  // fused FP32 adjoint decomposition
   int64_t fused_chunk = 0;
-  size_t hdr = 0, bbox = 0, flag = 0, bcnt = 0, list = 0, part_f = 0, part_q = 0, part_z = 0;
+  size_t hdr = 0, bbox = 0, flag = 0, bcnt = 0, list = 0, near_min = 0, part_f = 0, part_q = 0, part_z = 0;
   size_t slot_coef = 0, slot_hits = 0, slot_dp = 0, slot_z = 0, slot_den = 0, fpart = 0, wg_dp = 0;
   size_t fwd_total = 0;  // bytes the forward needs (a prefix of the full layout)
   size_t total = 0;      // bytes forward + backward need

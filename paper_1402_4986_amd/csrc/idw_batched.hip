@@ -49,6 +49,7 @@ struct BItem {
 };
 
 constexpr int kBQ = 4;       // queries per lane in the batched sweep
+constexpr int kBHdr = 16;    // header doubles per instance (HdrSlot layout)
 constexpr int kBboxBlocks = 32;
 
 // ---- per-instance extent and thresholds (scaled FP32 units), as in idw_forward ----
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(64) void kb_bbox_final(const BInst* __restrict__ in
     ext = fmax(ext, mx - mn);
   }
   for (int b = 0; b < nb; ++b) vm = fmax(vm, rec[b * kBboxStride + 6]);
-  fill_header(hdr + static_cast<int64_t>(i) * 8, ext, vm, I.p, true);
+  fill_header(hdr + static_cast<int64_t>(i) * kBHdr, ext, vm, I.p, true);
 }
 
 // ---- persistent sweep ----
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kWG) void kb_sweep(const BInst* __restrict__ inst, 
     if (w >= nitems) break;  // uniform exit: every wave of the workgroup sees the same w
     const BItem it = items[w];
     const BInst I = inst[it.inst];
-    const double* h = hdr + static_cast<int64_t>(it.inst) * 8;
+    const double* h = hdr + static_cast<int64_t>(it.inst) * kBHdr;
     if (I.dim == 3) {
       switch (I.pmode) {
         case PM_1: kb_item<3, PM_1>(I, it, h, part, tile); break;
@@ -251,11 +252,10 @@ __global__ __launch_bounds__(kWG) void kb_merge(const BInst* __restrict__ inst, 
     two_sum_acc(dh, dl, v.y);
   }
   const double num = nh + nl, den = dh + dl;
-  const double* h = hdr + static_cast<int64_t>(i) * 8;
-  const bool ok = den <= h[H_THR_S] && den > h[H_LO_S];
+  const double* h = hdr + static_cast<int64_t>(i) * kBHdr;
   I.out_z[q] = static_cast<float>(num / den);
   if (I.out_den) I.out_den[q] = den * h[H_DEN_UNIT];
-  flag[g] = ok ? 0 : 1;
+  flag[g] = route_of(den, h, false);
 }
 
 template <int DIM, int PM>
@@ -291,6 +291,48 @@ __device__ __forceinline__ void kb_fix_one(const BInst& I, int64_t q, double* re
   if (threadIdx.x == 0) {
     I.out_z[q] = static_cast<float>(th > 0 ? thz / static_cast<double>(th) : tn / td);
     if (I.out_den) I.out_den[q] = th > 0 ? __builtin_huge_val() : td;
+  }
+}
+
+// Nearest-distance check of the candidate queries (route F_CANDIDATE), one per workgroup:
+// the workgroup strides over its instance's data points, keeps the smallest squared
+// distance in the instance's scaled FP32 units (the same arithmetic as k_near_check) and
+// reduces it; within 1e-6 of the extent the query goes to FP64, otherwise its sweep result
+// stands.
+__global__ __launch_bounds__(kWG) void kb_near(const BInst* __restrict__ inst, int count,
+                                              const double* __restrict__ hdr, const int* __restrict__ list,
+                                              const int* __restrict__ cnt, uint8_t* __restrict__ route) {
+  __shared__ float red[kWG];
+  const int c = *cnt;
+  const int t = threadIdx.x;
+  for (int w = blockIdx.x; w < c; w += gridDim.x) {  // uniform over the workgroup
+    const int64_t g = list[w];
+    const int i = find_inst(inst, count, g);
+    const BInst I = inst[i];
+    const double* h = hdr + static_cast<int64_t>(i) * kBHdr;
+    const float s = static_cast<float>(h[H_SCALE]);
+    const float4 qr = I.query[g - I.q_off];
+    const float qx = qr.x * s, qy = qr.y * s, qz = qr.z * s;
+    float mn = __builtin_huge_valf();
+    for (int64_t j = t; j < I.n; j += kWG) {
+      const float4 d = I.data[j];
+      const float dx = qx - d.x * s, dy = qy - d.y * s;
+      float r2 = dx * dx;
+      r2 = fmaf(dy, dy, r2);
+      if (I.dim == 3) {
+        const float dz = qz - d.z * s;
+        r2 = fmaf(dz, dz, r2);
+      }
+      mn = r2 < mn ? r2 : mn;
+    }
+    red[t] = mn;
+    __syncthreads();
+    for (int o = kWG / 2; o > 0; o >>= 1) {
+      if (t < o) red[t] = red[t + o] < red[t] ? red[t + o] : red[t];
+      __syncthreads();
+    }
+    if (t == 0) route[g] = red[0] < static_cast<float>(h[H_NEAR_R2]) ? F_FP64 : F_FP32;
+    __syncthreads();
   }
 }
 
@@ -453,7 +495,7 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
   };
   const int64_t mt = std::max<int64_t>(P->mtot, 1);
   const int64_t nb = (mt + kCountBlock - 1) / kCountBlock;
-  P->o_hdr = take(sizeof(double) * 8 * count);
+  P->o_hdr = take(sizeof(double) * kBHdr * count);
   P->o_bbox = take(sizeof(double) * kBboxStride * kBboxBlocks * count);
   P->o_counter = take(sizeof(int) * 4);
   P->o_count = take(sizeof(int) * 4);
@@ -496,7 +538,10 @@ static hipError_t enqueue_batched(idw_plan* P, char* ws, hipStream_t st) {
   if (P->mtot > 0) {
     hipLaunchKernelGGL(kb_merge, dim3(static_cast<unsigned>((P->mtot + kWG - 1) / kWG)), dim3(kWG), 0, st, di,
                        P->count, P->mtot, hdr, part, flag);
-    hipError_t e = compact_flags(flag, P->mtot, bcnt, list, cnt, st);
+    hipError_t e = compact_flags(flag, P->mtot, bcnt, list, cnt, F_CANDIDATE, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kb_near, dim3(1024), dim3(kWG), 0, st, di, P->count, hdr, list, cnt, flag);
+    e = compact_flags(flag, P->mtot, bcnt, list, cnt, F_FP64, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kb_fixup, dim3(256), dim3(kWG), 0, st, di, P->count, list, cnt);
   }

@@ -250,14 +250,14 @@ __global__ __launch_bounds__(kWG) void k_bwd_qmerge(const double4* __restrict__ 
                                                     const T* __restrict__ grad_out,
                                                     const double* __restrict__ saved_den,
                                                     T* __restrict__ grad_q,
-                                                    double* __restrict__ wg_dp) {
+                                                    double* __restrict__ wg_dp,
+                                                    const uint8_t* __restrict__ route) {
   __shared__ double red[kWG];
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   double dpi = 0.0;
   if (i < m) {
     const double D = saved_den[i];
-    const bool ok = D <= hdr[H_THR_U] && D > hdr[H_LO_U];
-    if (ok) {
+    if (route[i] == F_FP32) {  // the others come from the FP64 fix-up
       double P[2] = {0.0, 0.0}, G[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
       for (int c = 0; c < split; ++c) {
         const double4 v = part[static_cast<int64_t>(c) * m + i];
@@ -325,14 +325,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
                                                   const double* __restrict__ hdr,
                                                   const T* __restrict__ grad_out,
                                                   const double* __restrict__ saved_den,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part,
+                                                  const uint8_t* __restrict__ route) {
   __shared__ P4<T> tile[2][kTile];
   const int tid = threadIdx.x;
   const int64_t x0 = static_cast<int64_t>(blockIdx.x) * (kWG * Q);
   const int64_t ib = static_cast<int64_t>(blockIdx.y) * chunk;
   const int64_t ie = (ib + chunk < m) ? ib + chunk : m;
   const T s = static_cast<T>(hdr[H_SCALE]);
-  const double thr = hdr[H_THR_U], lo = hdr[H_LO_U], unit = hdr[H_DEN_UNIT];
+  const double unit = hdr[H_DEN_UNIT];
 
   T xc[Q][3];
   int64_t xj[Q];
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
       ra[u] = T(0);
       if (i < ie) {
         const double D = saved_den[i];
-        if (D <= thr && D > lo) {  // flagged queries are left to the FP64 fix-up
+        if (route[i] == F_FP32) {  // the others are left to the FP64 fix-up
           T c[3] = {T(0), T(0), T(0)};
           Loader<T, DIM, L>::query(query, i, c);
           rc[u][0] = c[0];
@@ -428,7 +429,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
                                                    const T* __restrict__ saved_z,
                                                    const double* __restrict__ saved_den,
                                                    double* __restrict__ part_z,
-                                                   double* __restrict__ part_x) {
+                                                   double* __restrict__ part_x,
+                                                   const uint8_t* __restrict__ route) {
   __shared__ P4<T> tile[2][kTile];
   __shared__ T ztl[2][kTile];
   const int tid = threadIdx.x;
@@ -436,7 +438,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
   const int64_t ib = static_cast<int64_t>(blockIdx.y) * chunk;
   const int64_t ie = (ib + chunk < m) ? ib + chunk : m;
   const T s = static_cast<T>(hdr[H_SCALE]);
-  const double thr = hdr[H_THR_U], lo = hdr[H_LO_U], unit = hdr[H_DEN_UNIT];
+  const double unit = hdr[H_DEN_UNIT];
   const bool excl = (flags & 1u) != 0;
 
   T xc[Q][3], xv[Q];
@@ -469,7 +471,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
       live[u] = false;
       if (i < ie) {
         const double D = saved_den[i];
-        if (D <= thr && D > lo) {  // flagged queries are left to the FP64 fix-up
+        if (route[i] == F_FP32) {  // the others are left to the FP64 fix-up
           Loader<T, DIM, L>::query(query, i, rc[u]);
           ra[u] = static_cast<T>(static_cast<double>(grad_out[i]) / (D / unit));
           rz[u] = saved_z[i];
@@ -885,7 +887,7 @@ hipError_t launch_bwd_data_t(const BwdArgs& a, int split, int64_t chunk, double*
 #define IDW_BD_Q(QQ)                                                                        \
   case QQ:                                                                                  \
     hipLaunchKernelGGL((k_bwd_data<T, DIM, L, PM, QQ>), grid, dim3(kWG), 0, st, a.data,     \
-                       a.n, a.query, a.m, chunk, nhp, a.flags, a.hdr, go, a.saved_den, part); \
+                       a.n, a.query, a.m, chunk, nhp, a.flags, a.hdr, go, a.saved_den, part, a.route); \
     break;
   if constexpr (sizeof(T) == 4) {
     switch (Q) {
@@ -936,7 +938,7 @@ hipError_t launch_bwd_datax_t(const BwdArgs& a, int split, int64_t chunk, hipStr
   dim3 grid(static_cast<unsigned>((a.n + xpb - 1) / xpb), static_cast<unsigned>(split));
   hipLaunchKernelGGL((k_bwd_datax<T, DIM, L, PM, Q>), grid, dim3(kWG), 0, st, a.data, a.n, a.query, a.m,
                      chunk, static_cast<T>(-0.5 * a.p), a.flags, a.hdr, static_cast<const T*>(a.grad_out),
-                     static_cast<const T*>(a.saved_z), a.saved_den, a.part_z, a.part_x);
+                     static_cast<const T*>(a.saved_z), a.saved_den, a.part_z, a.part_x, a.route);
   return hipGetLastError();
 }
 
@@ -974,7 +976,7 @@ hipError_t launch_bwd_qmerge(const BwdArgs& a, int split, const double4* part, h
   dim3 grid(static_cast<unsigned>((a.m + kWG - 1) / kWG));
   hipLaunchKernelGGL((k_bwd_qmerge<T, DIM>), grid, dim3(kWG), 0, st, part, a.m, split, a.p, a.hdr,
                      static_cast<const T*>(a.grad_out), a.saved_den, static_cast<T*>(a.grad_q),
-                     a.wg_dp);
+                     a.wg_dp, a.route);
   return hipGetLastError();
 }
 

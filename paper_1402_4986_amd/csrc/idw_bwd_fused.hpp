@@ -124,7 +124,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
     DevPts data, int64_t n, DevPts query, int64_t m, int64_t chunk, int groups, float nhp, unsigned flags,
     const double* __restrict__ hdr, const float* __restrict__ saved_z, const float* __restrict__ grad_out,
     const double* __restrict__ saved_den, double4* __restrict__ part_q, double* __restrict__ part_z,
-    double* __restrict__ part_x) {
+    double* __restrict__ part_x, const uint8_t* __restrict__ route) {
   __shared__ P4<float> tile[2][2 * kFTile];   // batches stored twice in a row
   constexpr int PPT = kFTile / NT;            // tile points staged per thread
   __shared__ float zred[NT / 64][kFTile];    // per-wave dz sums of the current tile
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
   const int64_t jb = static_cast<int64_t>(blockIdx.y) * chunk;
   const int64_t je = (jb + chunk < n) ? jb + chunk : n;
   const float s = static_cast<float>(hdr[H_SCALE]);
-  const double thr = hdr[H_THR_U], lo = hdr[H_LO_U], unit = hdr[H_DEN_UNIT];
+  const double unit = hdr[H_DEN_UNIT];
   const bool excl = (flags & 1u) != 0;
   const int64_t qpb = static_cast<int64_t>(NT) * Q;
   const int64_t nqb = (m + qpb - 1) / qpb;
@@ -178,9 +178,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
       zq[k] = 0.f;
       aq[k] = 0.f;
       if (qi[k] < m) {
-        const double D = saved_den[qi[k]];
-        ok = D <= thr && D > lo;  // flagged queries are left to the FP64 fix-up
+        ok = route[qi[k]] == F_FP32;  // the others are left to the FP64 fix-up
         if (ok) {
+          const double D = saved_den[qi[k]];
           Loader<float, DIM, L>::query(query, qi[k], c);
           zq[k] = saved_z[qi[k]];
           aq[k] = static_cast<float>(static_cast<double>(grad_out[qi[k]]) / (D / unit));
@@ -296,7 +296,7 @@ hipError_t launch_bwd_fused_t(const BwdArgs& a, int groups, int ranges, int64_t 
 #define IDW_BF(DP, DQ, DX)                                                                          \
   hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ, DX>), grid, dim3(kFNT), 0, st, a.data, a.n, \
                      a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den,         \
-                     a.part_q, a.part_z, a.part_x)
+                     a.part_q, a.part_z, a.part_x, a.route)
   // The data-coordinate gradient is instantiated with both query-direction sums (they share
   // its per-pair factors); merges write only what was requested.
   if (ndx)

@@ -69,10 +69,9 @@ __global__ __launch_bounds__(kWG) void k_merge(const double2* __restrict__ part,
     two_sum_acc(dh, dl, v.y);
   }
   const double num = nh + nl, den = dh + dl;
-  const bool ok = den <= hdr[H_THR_S] && den > hdr[H_LO_S];
   out_z[i] = static_cast<T>(num / den);
   if (out_den) out_den[i] = den * hdr[H_DEN_UNIT];
-  flag[i] = ok ? 0 : 1;
+  flag[i] = route_of(den, hdr, false);
 }
 
 hipError_t merge_split(const double2* part, int64_t m, int split, const double* hdr, void* out_z,
@@ -87,14 +86,15 @@ hipError_t merge_split(const double2* part, int64_t m, int split, const double* 
   return hipGetLastError();
 }
 
-// Backward flag: the saved denominator (caller units) outside the FP32-safe range.
+// Backward route of each query from its saved denominator (caller units); candidates are
+// then settled by the same nearest-distance check as in the forward.
 __global__ __launch_bounds__(kWG) void k_flags_from_den(const double* __restrict__ den, int64_t m,
                                                         const double* __restrict__ hdr,
                                                         uint8_t* __restrict__ flag) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x;
   if (i >= m) return;
   const double d = den[i];
-  flag[i] = (d <= hdr[H_THR_U] && d > hdr[H_LO_U]) ? 0 : 1;
+  flag[i] = route_of(d, hdr, true);
 }
 
 hipError_t flags_from_den(const double* den, int64_t m, const double* hdr, uint8_t* flag,
@@ -104,26 +104,27 @@ hipError_t flags_from_den(const double* den, int64_t m, const double* hdr, uint8
   return hipGetLastError();
 }
 
-// ---- Deterministic, order-preserving compaction of flag bytes into an index list. ----
-// Block b owns flags [b*4096, (b+1)*4096); thread t owns 16 consecutive flags of it.
+// ---- Deterministic, order-preserving compaction of the queries whose route byte equals
+// `want` into an index list.  Block b owns bytes [b*4096, (b+1)*4096); thread t owns 16
+// consecutive bytes of it. ----
 constexpr int kPerThread = kCountBlock / kWG;
 
 __device__ __forceinline__ int local_count(const uint8_t* __restrict__ flag, int64_t m,
-                                           int64_t base) {
+                                           int64_t base, uint8_t want) {
   int c = 0;
 #pragma unroll
   for (int u = 0; u < kPerThread; ++u) {
     const int64_t i = base + u;
-    if (i < m) c += flag[i] ? 1 : 0;
+    if (i < m) c += flag[i] == want ? 1 : 0;
   }
   return c;
 }
 
 __global__ __launch_bounds__(kWG) void k_count(const uint8_t* __restrict__ flag, int64_t m,
-                                               int* __restrict__ bcnt) {
+                                               uint8_t want, int* __restrict__ bcnt) {
   __shared__ double red[kWG];
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kCountBlock + threadIdx.x * kPerThread;
-  const double c = block_sum(static_cast<double>(local_count(flag, m, base)), red);
+  const double c = block_sum(static_cast<double>(local_count(flag, m, base, want)), red);
   if (threadIdx.x == 0) bcnt[blockIdx.x] = static_cast<int>(c);
 }
 
@@ -154,12 +155,12 @@ __global__ __launch_bounds__(kWG) void k_scan(int* __restrict__ bcnt, int nb,
 }
 
 __global__ __launch_bounds__(kWG) void k_emit(const uint8_t* __restrict__ flag, int64_t m,
-                                              const int* __restrict__ boff,
+                                              uint8_t want, const int* __restrict__ boff,
                                               int* __restrict__ list) {
   __shared__ int buf[kWG];
   const int t = threadIdx.x;
   const int64_t base = static_cast<int64_t>(blockIdx.x) * kCountBlock + t * kPerThread;
-  const int c = local_count(flag, m, base);
+  const int c = local_count(flag, m, base, want);
   buf[t] = c;
   __syncthreads();
   for (int off = 1; off < kWG; off <<= 1) {
@@ -171,16 +172,16 @@ __global__ __launch_bounds__(kWG) void k_emit(const uint8_t* __restrict__ flag, 
   int pos = boff[blockIdx.x] + buf[t] - c;
   for (int u = 0; u < kPerThread; ++u) {
     const int64_t i = base + u;
-    if (i < m && flag[i]) list[pos++] = static_cast<int>(i);
+    if (i < m && flag[i] == want) list[pos++] = static_cast<int>(i);
   }
 }
 
 hipError_t compact_flags(const uint8_t* flag, int64_t m, int* bcnt, int* list, int* count,
-                         hipStream_t st) {
+                         uint8_t want, hipStream_t st) {
   const int nb = static_cast<int>((m + kCountBlock - 1) / kCountBlock);
-  hipLaunchKernelGGL(k_count, dim3(nb), dim3(kWG), 0, st, flag, m, bcnt);
+  hipLaunchKernelGGL(k_count, dim3(nb), dim3(kWG), 0, st, flag, m, want, bcnt);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kWG), 0, st, bcnt, nb, count);
-  hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kWG), 0, st, flag, m, bcnt, list);
+  hipLaunchKernelGGL(k_emit, dim3(nb), dim3(kWG), 0, st, flag, m, want, bcnt, list);
   return hipGetLastError();
 }
 

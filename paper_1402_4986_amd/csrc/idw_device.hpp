@@ -273,8 +273,31 @@ enum HdrSlot {
   H_LO_U = 5,      // lower flag threshold, caller units
   H_EXTENT = 6,    // data extent (largest side of the bounding box; 1 if degenerate)
   H_VMAX = 7,      // largest |value| of the data points
+  H_GEO_S = 8,     // near-coincidence threshold on the denominator, scaled units
+  H_GEO_U = 9,     // near-coincidence threshold, caller units
+  H_NEAR_R2 = 10,  // squared near-coincidence distance (1e-6 extent s)^2, scaled units
   H_COUNT_I = 32   // int slots start at byte 256: [0] flagged count
 };
+
+// Per-query route after a sweep (flag bytes):
+//  F_FP32       the sweep's result stands;
+//  F_CANDIDATE  the denominator exceeds (1e-6 extent)^-p: some data point may lie closer
+//               than 1e-6 of the extent, or many moderate weights add up to that much (the
+//               common case for p near 1 and large n); a check of the nearest distance
+//               decides between the other two routes;
+//  F_FP64       recomputed in FP64: an exact hit, a data point within 1e-6 of the extent,
+//               a denominator past the FP32-safe cap, FP32 underflow, or not finite.
+enum QueryRoute : uint8_t { F_FP32 = 0, F_CANDIDATE = 1, F_FP64 = 2 };
+
+// Route of a query from its denominator; `units` selects the scaled (sweep) or the caller
+// thresholds of the header.
+__device__ __forceinline__ uint8_t route_of(double den, const double* __restrict__ hdr, bool caller_units) {
+  const double cap = hdr[caller_units ? H_THR_U : H_THR_S];
+  const double lo = hdr[caller_units ? H_LO_U : H_LO_S];
+  const double geo = hdr[caller_units ? H_GEO_U : H_GEO_S];
+  if (!(den <= cap && den > lo)) return F_FP64;
+  return den > geo ? F_CANDIDATE : F_FP32;
+}
 
 // Per-workgroup partials of the extent kernels: [0..2] coordinate minima, [3..5] maxima,
 // [6] largest |value|, [7] unused.
@@ -283,35 +306,42 @@ constexpr int kBboxStride = 8;
 // Fills the header from the data extent and largest |value|.
 //  s = 2^-e with extent * s in [0.5, 1) for the FP32 sweep (exact scaling that keeps every
 //    weight of points inside the box far from FP32 overflow and underflow), 1 for FP64.
-//  A query is recomputed in FP64 when its denominator exceeds (1e-6 * extent)^-p (a data
-//  point closer than 1e-6 of the extent, or an exact hit) or is not above the lower
-//  threshold (FP32 underflow of the weights).  On the FP32 path the upper threshold is also
-//  capped at 2^80 / max(1, max|value|): then every weight is at most 2^80 / max(1, max|value|)
-//  and every distance at least 2^-21 (scaled units), which bounds every FP32 term and sum of
-//  the forward and adjoint sweeps below 2^125.  Thresholds are finite: for large p,
-//  (1e-6 * extent)^-p overflows, and an infinite threshold would pass an infinite denominator.
+//  Near-coincidence: a data point closer than 1e-6 of the extent puts the denominator above
+//  (1e-6 * extent)^-p, so queries above it are candidates whose nearest distance is then
+//  checked against 1e-6 * extent (route_of, k_near_check).
+//  Hard cap: a denominator that is not finite, or not above the lower threshold (FP32
+//  underflow of the weights), is recomputed in FP64; on the FP32 path so is one above
+//  2^80 / max(1, max|value|): below it every weight is at most that and every distance at
+//  least 2^-21 (scaled units), which bounds every FP32 term and sum of the forward and
+//  adjoint sweeps below 2^125.  Thresholds are finite: for large p, (1e-6 * extent)^-p
+//  overflows, and an infinite threshold would pass an infinite denominator.
 __device__ inline void fill_header(double* __restrict__ h, double ext, double vmax, double p,
                                    bool f32s) {
   if (!(ext > 0.0) || !(ext < __builtin_huge_val())) ext = 1.0;
   double s = 1.0;
-  double thr_s = fmin(pow(1e-6 * ext, -p), __DBL_MAX__);
+  double cap_s = __DBL_MAX__;
   double lo_s = 0.0;
   if (f32s) {
     int e = 0;
     (void)frexp(ext, &e);
     s = ldexp(1.0, -e);
-    thr_s = fmin(pow(1e-6 * ext * s, -p), ldexp(1.0, 80) / fmax(1.0, vmax));
+    cap_s = ldexp(1.0, 80) / fmax(1.0, vmax);
     lo_s = ldexp(1.0, -60);
   }
+  const double near = 1e-6 * ext * s;
+  const double geo_s = fmin(pow(near, -p), __DBL_MAX__);
   const double unit = pow(s, p);
   h[H_SCALE] = s;
-  h[H_THR_S] = thr_s;
+  h[H_THR_S] = cap_s;
   h[H_LO_S] = lo_s;
   h[H_DEN_UNIT] = unit;
-  h[H_THR_U] = fmin(thr_s * unit, __DBL_MAX__);
+  h[H_THR_U] = fmin(cap_s * unit, __DBL_MAX__);
   h[H_LO_U] = lo_s * unit;
   h[H_EXTENT] = ext;
   h[H_VMAX] = vmax;
+  h[H_GEO_S] = geo_s;
+  h[H_GEO_U] = fmin(geo_s * unit, __DBL_MAX__);
+  h[H_NEAR_R2] = near * near;
 }
 
 }  // namespace idw

@@ -132,10 +132,9 @@ template <typename T>
 __device__ __forceinline__ void fwd_finish(int64_t i, double num, double den, const double* hdr,
                                            T* __restrict__ out_z, double* __restrict__ out_den,
                                            uint8_t* __restrict__ out_flag) {
-  const bool ok = den <= hdr[H_THR_S] && den > hdr[H_LO_S];
   out_z[i] = static_cast<T>(num / den);
   if (out_den) out_den[i] = den * hdr[H_DEN_UNIT];
-  out_flag[i] = ok ? 0 : 1;
+  out_flag[i] = route_of(den, hdr, false);
 }
 
 // Register-blocking and occupancy knobs of a sweep kernel: UNR = unroll of the per-record
@@ -223,6 +222,137 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
       else
         part[static_cast<int64_t>(blockIdx.y) * m + qi[k]] = make_double2(num, den);
     }
+  }
+}
+
+// Nearest-distance check of the candidate queries (route F_CANDIDATE, compacted in `list`,
+// *count of them), in three kernels:
+//  k_near_init   sets each candidate's minimum to +inf;
+//  k_near_check  takes work items (block of kWG * Q candidates, data chunk) in turn: the
+//                data chunk goes through LDS tiles as in the forward sweep, each query keeps
+//                its smallest squared distance in scaled units (the leave-one-out self pair
+//                excluded) and folds it into its minimum by an integer atomic min on the
+//                bits of the non-negative value (order-independent, so deterministic).  The
+//                data range is cut into as many chunks as keep about kNearGrid workgroups
+//                busy when the candidates are few, none when they fill the grid;
+//  k_near_finish gives a candidate with a data point closer than 1e-6 of the extent
+//                F_FP64, the others F_FP32 (their sweep results stand).
+// 5 VALU operations per pair (2 sub, mul + fma, min).
+constexpr int kNearGrid = 1024;      // workgroups of the nearest-distance check
+constexpr int kNearMinChunk = 8192;  // fewest data points per chunk
+
+template <typename T>
+__device__ __forceinline__ unsigned long long min_bits(T v) {  // v >= 0: bits order as values
+  if constexpr (sizeof(T) == 4)
+    return static_cast<unsigned long long>(__builtin_bit_cast(unsigned int, v));
+  else
+    return __builtin_bit_cast(unsigned long long, v);
+}
+template <typename T>
+__device__ __forceinline__ T from_min_bits(unsigned long long b) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(float, static_cast<unsigned int>(b));
+  else
+    return __builtin_bit_cast(double, b);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_near_init(const int* __restrict__ list, const int* __restrict__ count,
+                                                   unsigned long long* __restrict__ minb) {
+  const int cnt = *count;
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) minb[list[i]] = min_bits(infT<T>());
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_near_finish(const int* __restrict__ list, const int* __restrict__ count,
+                                                     const unsigned long long* __restrict__ minb,
+                                                     const double* __restrict__ hdr, uint8_t* __restrict__ route) {
+  const int cnt = *count;
+  const T near = static_cast<T>(hdr[H_NEAR_R2]);
+  for (int i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) {
+    const int q = list[i];
+    route[q] = from_min_bits<T>(minb[q]) < near ? F_FP64 : F_FP32;
+  }
+}
+
+template <typename T, int DIM, int L, int Q, bool EXCL>
+__global__ __launch_bounds__(kWG) void k_near_check(DevPts data, int64_t n, DevPts query,
+                                                    const int* __restrict__ list,
+                                                    const int* __restrict__ count,
+                                                    const double* __restrict__ hdr,
+                                                    unsigned long long* __restrict__ minb) {
+  __shared__ P4<T> tile[2][kTile];
+  const int64_t cnt = *count;
+  const int tid = threadIdx.x;
+  const T s = static_cast<T>(hdr[H_SCALE]);
+  constexpr int64_t kQB = static_cast<int64_t>(kWG) * Q;
+  const int64_t nblk = (cnt + kQB - 1) / kQB;
+  if (nblk == 0) return;
+  // data chunks per candidate block: fill the grid when the candidates are few
+  int64_t C = kNearGrid / nblk;
+  const int64_t cmax = (n + kNearMinChunk - 1) / kNearMinChunk;
+  if (C > cmax) C = cmax;
+  if (C < 1) C = 1;
+  const int64_t len = ((n + C - 1) / C + kTile - 1) / kTile * kTile;
+  C = (n + len - 1) / len;
+  const int64_t total = nblk * C;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {  // uniform over the workgroup
+    const int64_t b0 = (w / C) * kQB;
+    const int64_t jb = (w % C) * len;
+    const int64_t je = jb + len < n ? jb + len : n;
+    T qc[Q][3], mn[Q];
+    int64_t qi[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int64_t slot = b0 + tid + static_cast<int64_t>(k) * kWG;
+      qi[k] = slot < cnt ? list[slot] : -1;
+      T c[3] = {T(0), T(0), T(0)};
+      if (qi[k] >= 0) Loader<T, DIM, L>::query(query, qi[k], c);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) qc[k][d] = c[d] * s;
+      mn[k] = infT<T>();
+    }
+    T rc[2][3], rv[2];
+    auto fetch = [&](int t) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int64_t j = jb + static_cast<int64_t>(t) * kTile + u * kWG + tid;
+        if (j < je) {
+          Loader<T, DIM, L>::data(data, j, rc[u], rv[u]);
+        } else {  // padding record: infinitely far
+          rc[u][0] = rc[u][1] = rc[u][2] = infT<T>();
+          rv[u] = T(0);
+        }
+      }
+    };
+    auto put = [&](int b) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) tile[b][u * kWG + tid] = stage<T, DIM>(rc[u], rv[u], s);
+    };
+    const int ntiles = static_cast<int>((je - jb + kTile - 1) / kTile);
+    fetch(0);
+    put(0);
+    __syncthreads();
+    for (int t = 0; t < ntiles; ++t) {
+      if (t + 1 < ntiles) fetch(t + 1);
+      const int64_t jt = jb + static_cast<int64_t>(t) * kTile;
+      const P4<T>* tl = tile[t & 1];
+#pragma unroll 4
+      for (int jj = 0; jj < kTile; ++jj) {
+        const P4<T> d = tl[jj];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          T r2 = sqdist<T, DIM>(qc[k], d);
+          if constexpr (EXCL) r2 = (jt + jj == qi[k]) ? infT<T>() : r2;
+          mn[k] = r2 < mn[k] ? r2 : mn[k];
+        }
+      }
+      if (t + 1 < ntiles) put((t + 1) & 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+      if (qi[k] >= 0) atomicMin(&minb[qi[k]], min_bits(mn[k]));
   }
 }
 
@@ -456,6 +586,27 @@ template <int L>
 hipError_t launch_fwd_fixup(const FwdArgs& a, bool f64, hipStream_t st) {
   if (f64) return a.dim == 3 ? launch_fwd_fixup_pm<double, 3, L>(a, st) : launch_fwd_fixup_pm<double, 2, L>(a, st);
   return a.dim == 3 ? launch_fwd_fixup_pm<float, 3, L>(a, st) : launch_fwd_fixup_pm<float, 2, L>(a, st);
+}
+
+template <typename T, int DIM, int L>
+hipError_t launch_near_check_t(const NearArgs& a, hipStream_t st) {
+  constexpr int Q = sizeof(T) == 4 ? 4 : 2;
+  const unsigned gl = static_cast<unsigned>(a.m < 64 * kWG ? (a.m + kWG - 1) / kWG + 1 : 64);
+  hipLaunchKernelGGL((k_near_init<T>), dim3(gl), dim3(kWG), 0, st, a.list, a.count, a.minb);
+  if (a.excl)
+    hipLaunchKernelGGL((k_near_check<T, DIM, L, Q, true>), dim3(kNearGrid), dim3(kWG), 0, st, a.data, a.n,
+                       a.query, a.list, a.count, a.hdr, a.minb);
+  else
+    hipLaunchKernelGGL((k_near_check<T, DIM, L, Q, false>), dim3(kNearGrid), dim3(kWG), 0, st, a.data, a.n,
+                       a.query, a.list, a.count, a.hdr, a.minb);
+  hipLaunchKernelGGL((k_near_finish<T>), dim3(gl), dim3(kWG), 0, st, a.list, a.count, a.minb, a.hdr, a.route);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_near_check(const NearArgs& a, hipStream_t st) {
+  if (a.f64) return a.dim == 3 ? launch_near_check_t<double, 3, L>(a, st) : launch_near_check_t<double, 2, L>(a, st);
+  return a.dim == 3 ? launch_near_check_t<float, 3, L>(a, st) : launch_near_check_t<float, 2, L>(a, st);
 }
 
 template <int L>

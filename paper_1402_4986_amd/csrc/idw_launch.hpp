@@ -59,6 +59,7 @@ struct BwdArgs {
   const void* grad_out = nullptr;
   const void* saved_z = nullptr;
   const double* saved_den = nullptr;
+  const uint8_t* route = nullptr;  // [m] settled QueryRoute of each query
   void* grad_z = nullptr;
   void* grad_q = nullptr;
   void* grad_x = nullptr;
@@ -72,6 +73,22 @@ struct BwdArgs {
   double* slot_den = nullptr;   // [m] per flagged slot: FP64 denominator
   int fix_cmax = 1;
   double4* fpart = nullptr;     // [kFixGrid] fix-up chunk partials
+};
+
+// The nearest-distance check of candidate queries (k_near_check).
+struct NearArgs {
+  DevPts data;
+  int64_t n = 0;
+  DevPts query;
+  int64_t m = 0;  // queries in all (bounds the candidates)
+  int dim = 2;
+  bool f64 = false;
+  bool excl = false;
+  const int* list = nullptr;   // candidate query indices
+  const int* count = nullptr;  // number of candidates (device)
+  const double* hdr = nullptr;
+  uint8_t* route = nullptr;    // [m] QueryRoute, settled for the candidates
+  unsigned long long* minb = nullptr;  // [m] per-candidate minimum (bits), scratch
 };
 
 constexpr int kTile = 512;        // data points staged in LDS per tile (2 per thread)
@@ -88,7 +105,8 @@ constexpr int kCountBlock = 4096; // flags per compaction block (16 per thread)
   hipError_t bwd_data_##NAME(const BwdArgs& a, bool f64, hipStream_t st);        \
   hipError_t bwd_datax_##NAME(const BwdArgs& a, bool f64, hipStream_t st);       \
   hipError_t bwd_fixup_##NAME(const BwdArgs& a, bool f64, hipStream_t st);      \
-  hipError_t bwd_fused_##NAME(const BwdArgs& a, hipStream_t st);
+  hipError_t bwd_fused_##NAME(const BwdArgs& a, hipStream_t st);                 \
+  hipError_t near_check_##NAME(const NearArgs& a, hipStream_t st);
 
 IDW_DECLARE_LAYOUT(soa)
 IDW_DECLARE_LAYOUT(aos)
@@ -102,7 +120,7 @@ hipError_t bbox_final(const double* part, int nblocks, int dim, double p, bool f
 hipError_t merge_split(const double2* part, int64_t m, int split, const double* hdr,
                        void* out_z, bool f64, double* out_den, uint8_t* flag, hipStream_t st);
 hipError_t compact_flags(const uint8_t* flag, int64_t m, int* bcnt, int* list, int* count,
-                         hipStream_t st);
+                         uint8_t want, hipStream_t st);
 hipError_t flags_from_den(const double* den, int64_t m, const double* hdr, uint8_t* flag,
                           hipStream_t st);
 hipError_t bwd_qmerge(const BwdArgs& a, bool f64, hipStream_t st);

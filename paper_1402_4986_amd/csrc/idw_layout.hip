@@ -61,6 +61,10 @@ hipError_t IDW_CAT(bwd_fixup_, IDW_LAYOUT_NAME)(const BwdArgs& a, bool f64, hipS
   return a.dim == 3 ? bwd_fix_pm<float, 3, IDW_LAYOUT>(a, st) : bwd_fix_pm<float, 2, IDW_LAYOUT>(a, st);
 }
 
+hipError_t IDW_CAT(near_check_, IDW_LAYOUT_NAME)(const NearArgs& a, hipStream_t st) {
+  return launch_near_check<IDW_LAYOUT>(a, st);
+}
+
 hipError_t IDW_CAT(bwd_fused_, IDW_LAYOUT_NAME)(const BwdArgs& a, hipStream_t st) {
   return a.dim == 3 ? bwd_fused_pm<3, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st)
                     : bwd_fused_pm<2, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st);

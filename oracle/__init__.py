@@ -36,24 +36,38 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
-def _load():
+def load_library(path: str):
+    """Loads an oracle library built from idw_oracle.c (or, in the mutation tests, from a
+    copy of it with a planted mistake) and declares its prototypes."""
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int64)
+    lib.idw_oracle_forward.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
+                                       ctypes.c_double, ip, dp, dp, dp, ip]
+    lib.idw_oracle_forward.restype = ctypes.c_int
+    lib.idw_oracle_backward.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
+                                        ctypes.c_double, ip, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+    lib.idw_oracle_backward.restype = ctypes.c_int
+    lib.idw_oracle_backward_x.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
+                                          ctypes.c_double, ip, dp, dp, dp]
+    lib.idw_oracle_backward_x.restype = ctypes.c_int
+    return lib
+
+
+def compile_source(src: str, out: str) -> str:
+    """Builds a shared library from a C source file with the oracle's flags."""
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-o", out, src, "-lm"])
+    return out
+
+
+def _load(lib=None):
     global _lib
+    if lib is not None:
+        return lib
     with _lock:
         if _lib is None:
             build()
-            lib = ctypes.CDLL(_LIB_PATH)
-            dp = ctypes.POINTER(ctypes.c_double)
-            ip = ctypes.POINTER(ctypes.c_int64)
-            lib.idw_oracle_forward.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
-                                               ctypes.c_double, ip, dp, dp, dp, ip]
-            lib.idw_oracle_forward.restype = ctypes.c_int
-            lib.idw_oracle_backward.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
-                                                ctypes.c_double, ip, dp, dp, dp, dp, dp, dp, dp, dp, dp]
-            lib.idw_oracle_backward.restype = ctypes.c_int
-            lib.idw_oracle_backward_x.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, ctypes.c_int64, dp,
-                                                  ctypes.c_double, ip, dp, dp, dp]
-            lib.idw_oracle_backward_x.restype = ctypes.c_int
-            _lib = lib
+            _lib = load_library(_LIB_PATH)
     return _lib
 
 
@@ -79,13 +93,14 @@ def _prep(x, z, q, self_index):
     return x, z, q, si
 
 
-def forward(x, z, q, p, self_index=None):
+def forward(x, z, q, p, self_index=None, lib=None):
     """Eq. 1 over every data point.  Returns dict(Z, D, S, H) of numpy arrays.
 
     x: [n, dim] data coordinates, z: [n] data values, q: [m, dim] queries, p > 0.
     self_index: optional [m] data index left out per query (leave-one-out).
+    lib: an alternative library from load_library (default: the built oracle).
     """
-    lib = _load()
+    lib = _load(lib)
     x, z, q, si = _prep(x, z, q, self_index)
     m = q.shape[0]
     Z = np.empty(m)
@@ -99,14 +114,14 @@ def forward(x, z, q, p, self_index=None):
     return {"Z": Z, "D": D, "S": S, "H": H}
 
 
-def backward(x, z, q, p, g, self_index=None):
+def backward(x, z, q, p, g, self_index=None, lib=None):
     """Analytic adjoint of Eq. 1.
 
     Returns dict(dz, dp, dq, dz_scale, dp_scale, dq_scale, dp_cond, dq_cond): the *_scale
     entries are the sums of absolute terms; dp_cond / dq_cond the uncentred sums that
     measure how far a relative perturbation of the values moves dp / dq.
     """
-    lib = _load()
+    lib = _load(lib)
     x, z, q, si = _prep(x, z, q, self_index)
     g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
     n, dim = x.shape
@@ -129,13 +144,13 @@ def backward(x, z, q, p, g, self_index=None):
             "dq_scale": dqs, "dp_cond": float(dpc[0]), "dq_cond": dqc}
 
 
-def backward_x(x, z, q, p, g, self_index=None):
+def backward_x(x, z, q, p, g, self_index=None, lib=None):
     """Adjoint with respect to the data coordinates: dict(dx [n, dim], dx_cond [n]).
 
     dx_cond is the uncentred sum (|z_j| + |Z_i| in place of z_j - Z_i) that bounds how far
     a relative perturbation of the values moves each row of dx.
     """
-    lib = _load()
+    lib = _load(lib)
     x, z, q, si = _prep(x, z, q, self_index)
     g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
     n, dim = x.shape

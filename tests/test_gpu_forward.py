@@ -177,3 +177,29 @@ def test_full_size_plain2d_f64_10k_every_query(layout, plain2d_10k):
     Z, D = gpu_forward(x, z, q, 2.0, layout, "f64")
     assert np.max(scaled_err(Z, ref)) <= TOL["f64"]
     np.testing.assert_allclose(D, ref["D"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_collinear_data_and_far_offsets(dim):
+    # Data on a line (every coordinate but the first constant), queries off it: the extent
+    # comes from one axis only.
+    r = np.random.default_rng(14)
+    n, m = 2000, 400
+    x = np.zeros((n, dim))
+    x[:, 0] = r.random(n)
+    x[:, 1:] = 0.3
+    z = np.sin(4 * x[:, 0]) + r.normal(0, 0.1, n)
+    q = r.random((m, dim))
+    q[:5] = x[:5]
+    x, z, q = (a.astype(np.float32).astype(np.float64) for a in (x, z, q))
+    Z, _ = gpu_forward(x, z, q, 2.0, "aoas", "f32")
+    ref = oracle.forward(x, z, q, 2.0)
+    assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
+    # FP32 records far from the origin (offset 1e6, extent 1e3): differences of nearby
+    # coordinates are exact, so the FP32 sweep keeps its accuracy without centring.
+    x2 = (1e6 + 1e3 * r.random((n, dim))).astype(np.float32).astype(np.float64)
+    q2 = (1e6 + 1e3 * r.random((m, dim))).astype(np.float32).astype(np.float64)
+    z2 = r.normal(size=n).astype(np.float32).astype(np.float64)
+    Z2, _ = gpu_forward(x2, z2, q2, 2.0, "aoas", "f32")
+    ref2 = oracle.forward(x2, z2, q2, 2.0)
+    assert np.max(scaled_err(Z2, ref2)) <= TOL["f32"]

@@ -129,7 +129,7 @@ def main():
     ap.add_argument("--layout", default="aoas", choices=["soa", "aos", "aoas", "hybrid", "soaos"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--no-layouts", action="store_true", help="skip the per-layout forward timings")
-    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--cpu-sample", type=int, default=200)
     ap.add_argument("--cpu-sample-per-core", type=int, default=24)
     ap.add_argument("--separate-adjoint", action="store_true",
                     help="run the adjoint as separate query- and data-direction sweeps")

@@ -125,6 +125,17 @@ static bool same_query_layout(int a, int b) {
   return canon(a) == canon(b);
 }
 
+int validate_config(const idw_config* cfg) {
+  if (!cfg) return IDW_OK;
+  for (int k = 0; k < 3; ++k)
+    if (cfg->reserved[k] != 0) return fail(IDW_EINVAL, "idw_config.reserved[%d] must be zero", k);
+  if (cfg->queries_per_lane < 0 || cfg->split < 0 || cfg->batch_chunk < 0 || cfg->batch_workgroups < 0)
+    return fail(IDW_EINVAL, "idw_config fields must not be negative");
+  if (cfg->separate_adjoint != 0 && cfg->separate_adjoint != 1)
+    return fail(IDW_EINVAL, "idw_config.separate_adjoint must be 0 or 1");
+  return IDW_OK;
+}
+
 int validate_common(const idw_points* data, const idw_points* query, double p, int precision,
                     uint32_t flags) {
   if (!known_precision(precision))
@@ -402,6 +413,7 @@ int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t 
   if (!bytes) return fail(IDW_EINVAL, "bytes is null");
   int rc = validate_common(data, query, 2.0, precision, flags & ~IDW_EXCLUDE_SELF);
   if (rc) return rc;
+  if ((rc = validate_config(cfg))) return rc;
   const WsPlan w = plan_workspace(data, query, precision, cfg);
   *bytes = (flags & IDW_NEED_DX) ? w.total_x
            : (flags & (IDW_NEED_DZ | IDW_NEED_DP | IDW_NEED_DQ)) ? w.total
@@ -415,6 +427,7 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   clear_error();
   int rc = validate_common(data, query, p, precision, flags);
   if (rc) return rc;
+  if ((rc = validate_config(cfg))) return rc;
   if (flags & ~IDW_EXCLUDE_SELF) return fail(IDW_EINVAL, "idw_forward accepts only IDW_EXCLUDE_SELF");
   if (cfg && cfg->queries_per_lane) {
     const int q = cfg->queries_per_lane;
@@ -479,6 +492,7 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
   clear_error();
   int rc = validate_common(data, query, p, precision, flags);
   if (rc) return rc;
+  if ((rc = validate_config(cfg))) return rc;
   const bool ndz = flags & IDW_NEED_DZ, ndp = flags & IDW_NEED_DP, ndq = flags & IDW_NEED_DQ;
   const bool ndx = flags & IDW_NEED_DX;
   if (!(ndz || ndp || ndq || ndx)) return fail(IDW_EINVAL, "no gradient requested (IDW_NEED_* flags)");

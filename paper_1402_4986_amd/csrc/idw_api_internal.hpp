@@ -37,6 +37,7 @@ int check_device();
 int validate_points(const idw_points* P, int precision, bool is_data, const char* what);
 int validate_common(const idw_points* data, const idw_points* query, double p, int precision,
                     uint32_t flags);
+int validate_config(const idw_config* cfg);
 int pmode_of(double p);
 WsPlan plan_workspace(const idw_points* data, const idw_points* query, int precision,
                       const idw_config* cfg);

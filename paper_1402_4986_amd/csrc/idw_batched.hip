@@ -406,6 +406,7 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
   *out_plan = nullptr;
   if (!instances || count <= 0) return fail(IDW_EINVAL, "at least one instance is required");
   if (precision != IDW_FP32) return fail(IDW_EUNSUPPORTED, "batched plans run the FP32 sweep only");
+  if (const int rc0 = validate_config(cfg)) return rc0;
   const int chunk_target =
       (cfg && cfg->batch_chunk > 0) ? static_cast<int>((cfg->batch_chunk + kTile - 1) / kTile * kTile) : 16384;
   const int grid_req = (cfg && cfg->batch_workgroups > 0) ? cfg->batch_workgroups : 0;

@@ -211,3 +211,24 @@ def test_kahan_precision_is_fp32_storage_with_its_own_limits(lib):
     arr[0].p = 2.0
     arr[0].out_z = 0x30000000
     assert lib.idw_batched_plan_create(arr, 1, _lib.FP32_KAHAN, None, ctypes.byref(plan)) == _lib.IDW_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("field,value", [("reserved", 1), ("split", -1), ("queries_per_lane", -4),
+                                         ("batch_chunk", -1), ("separate_adjoint", 2)])
+def test_config_fields_are_validated(lib, field, value):
+    d = _pts(1000, 2, _lib.AOAS)
+    q = _pts(500, 2, _lib.AOAS, base=0x20000000)
+    cfg = _lib.IdwConfig()
+    if field == "reserved":
+        cfg.reserved[1] = value
+    else:
+        setattr(cfg, field, value)
+    b = ctypes.c_size_t()
+    assert lib.idw_workspace_size(ctypes.byref(d), ctypes.byref(q), _lib.FP32, 0, ctypes.byref(cfg),
+                                  ctypes.byref(b)) == _lib.IDW_EINVAL
+    rc = lib.idw_forward(ctypes.byref(d), ctypes.byref(q), 2.0, _lib.FP32, 0, 0x8000000, None, 0x4000000,
+                         1 << 30, None, ctypes.byref(cfg))
+    assert rc == _lib.IDW_EINVAL
+    rc = lib.idw_backward(ctypes.byref(d), ctypes.byref(q), 2.0, _lib.FP32, _lib.NEED_DZ, 1, 1, 1, 0x9000000,
+                          None, None, None, 0x4000000, 1 << 30, None, ctypes.byref(cfg))
+    assert rc == _lib.IDW_EINVAL

@@ -21,10 +21,15 @@
  *    enqueued and a non-zero status is returned; idw_last_error() describes it.  Input
  *    values are not scanned: NaN or infinite coordinates/values give undefined results.
  *  - Results are bitwise reproducible for fixed inputs, sizes and configuration (no
- *    floating-point atomics; every reduction has a fixed order).
- *  - Element type follows the precision: IDW_FP32 reads and writes float arrays,
- *    IDW_FP64 reads and writes double arrays.  Denominators (out_den, saved_den) and
- *    grad_p are always double.
+ *    floating-point atomics; every sum has a fixed order; the only atomics are integer
+ *    ones whose result does not depend on their order: a minimum and a work counter).
+ *  - Element type follows the precision: IDW_FP32 and IDW_FP32_KAHAN read and write float
+ *    arrays, IDW_FP64 double arrays.  Denominators (out_den, saved_den) and grad_p are
+ *    always double.
+ *  - FP64 recomputation: a query with a data point closer than 1e-6 of the data extent
+ *    (exact hits included), or whose FP32 sums could leave the FP32 range (large p or
+ *    large |values|), is recomputed in FP64; the denominator nominates candidates and a
+ *    nearest-distance check settles them.
  */
 #ifndef IDW_H
 #define IDW_H
@@ -100,7 +105,9 @@ typedef struct idw_points {
  *   separate_adjoint  idw_backward, FP32: 1 = run the query-direction and data-direction
  *                     sweeps separately instead of the fused sweep (same results within
  *                     the stated tolerances; for comparison)
- *   reserved          must be zero */
+ *   reserved          must be zero
+ * Negative fields, non-zero reserved fields and separate_adjoint outside {0, 1} are
+ * rejected with IDW_EINVAL. */
 typedef struct idw_config {
   int32_t queries_per_lane;
   int32_t split;

@@ -27,9 +27,20 @@
  *    arrays, IDW_FP64 double arrays.  Denominators (out_den, saved_den) and grad_p are
  *    always double.
  *  - FP64 recomputation: a query with a data point closer than 1e-6 of the data extent
- *    (exact hits included), or whose FP32 sums could leave the FP32 range (large p or
- *    large |values|), is recomputed in FP64; the denominator nominates candidates and a
- *    nearest-distance check settles them.
+ *    (exact hits included), or whose FP32 sums could leave the FP32 range (large |values|,
+ *    or large p with the direct weights), is recomputed in FP64; the denominator
+ *    nominates candidates and a nearest-distance check settles them.
+ *  - Large p in FP32 (p >= 6): the FP32 sweeps take each query's weights relative to a
+ *    power of two sigma near its largest one, w' = (d^2 sigma)^(-p/2), so that weights
+ *    far outside the FP32 range stay on the FP32 path.  The forward first finds every
+ *    query's nearest squared distance (one more pass over all pairs, about 5 operations
+ *    each) and takes sigma from it; the adjoint takes sigma from the saved denominator.
+ *    Such queries return to FP64 only when max|value| > 2^32 (then all of them) or when
+ *    the query's denominator is below 2^(-10 p) in units where the data extent is in
+ *    [1/2, 1) (no data point within about 2^10 extents).  A weight below FLT_MIN relative
+ *    to its query's largest may be flushed to zero: a value gradient dL/dz_j can lose up
+ *    to |g_i| 2^-126 per query i.  With separate_adjoint = 1 the adjoint keeps the direct
+ *    weights and their FP64 routing.
  */
 #ifndef IDW_H
 #define IDW_H
@@ -104,7 +115,8 @@ typedef struct idw_points {
  *   batch_workgroups  batched plans: persistent workgroups (default 2 per compute unit)
  *   separate_adjoint  idw_backward, FP32: 1 = run the query-direction and data-direction
  *                     sweeps separately instead of the fused sweep (same results within
- *                     the stated tolerances; for comparison)
+ *                     the stated tolerances; for comparison).  These sweeps use the direct
+ *                     weights at every p (see "Large p in FP32").
  *   reserved          must be zero
  * Negative fields, non-zero reserved fields and separate_adjoint outside {0, 1} are
  * rejected with IDW_EINVAL. */
@@ -167,7 +179,9 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
  * dZ_i/dq_i = -(p/D_i) sum_j (w_ij / d_ij^2) (z_j - Z_i)(q_i - x_j),
  * dZ_i/dx_j = (p/D_i)(w_ij / d_ij^2)(z_j - Z_i)(q_i - x_j); at an exact hit with h
  * coincident points, dZ_i/dz_j = 1/h for each of them and the other terms are 0.
- * Queries within 1e-6 of the extent of a data point are handled in FP64. */
+ * Queries within 1e-6 of the extent of a data point are handled in FP64.  In FP32 with
+ * p >= 6 every request (any combination of IDW_NEED_* bits) runs in the fused sweep with
+ * relative weights unless cfg->separate_adjoint is 1. */
 int idw_backward(const idw_points* data, const idw_points* query, double p, int32_t precision,
                  uint32_t flags, const void* grad_out, const void* saved_z,
                  const double* saved_den, void* grad_z, double* grad_p, void* grad_q,

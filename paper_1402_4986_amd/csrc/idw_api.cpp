@@ -277,14 +277,33 @@ int check_workspace(void* ws, size_t bytes, size_t need) {
   return IDW_OK;
 }
 
-// Enqueues the extent/threshold header computation.
-hipError_t enqueue_header(const idw_points* data, double p, bool f64, char* ws, const WsPlan& w,
+// Enqueues the extent/threshold header computation (rel: thresholds of the relative-weight
+// FP32 sweeps).
+hipError_t enqueue_header(const idw_points* data, double p, bool f64, bool rel, char* ws, const WsPlan& w,
                           hipStream_t st) {
   hipError_t e = fns(data->layout).bbox(dev_pts(data), data->n, data->dim, f64,
                                         reinterpret_cast<double*>(ws + w.bbox), w.nbbox, st);
   if (e != hipSuccess) return e;
-  return bbox_final(reinterpret_cast<double*>(ws + w.bbox), w.nbbox, data->dim, p, !f64,
+  return bbox_final(reinterpret_cast<double*>(ws + w.bbox), w.nbbox, data->dim, p, !f64, rel,
                     reinterpret_cast<double*>(ws + w.hdr), st);
+}
+
+// Nearest squared distance of every query (FP32 bits, scaled units) into the near_min
+// section: the relative-weight forward sweep takes each query's sigma from it.
+static hipError_t nearest_all(const LayoutFns& F, const idw_points* data, const idw_points* query, bool excl,
+                              char* ws, const WsPlan& w, hipStream_t st) {
+  NearArgs na;
+  na.data = dev_pts(data);
+  na.n = data->n;
+  na.query = dev_pts(query);
+  na.m = query->n;
+  na.dim = data->dim;
+  na.f64 = false;
+  na.excl = excl;
+  na.all = true;
+  na.hdr = reinterpret_cast<const double*>(ws + w.hdr);
+  na.minb = reinterpret_cast<unsigned long long*>(ws + w.near_min);
+  return F.near_check(na, st);
 }
 
 // Settles the route of every query after a sweep (or from the saved denominators): the
@@ -458,6 +477,9 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   a.flags = flags;
   a.q_per_lane = w.qf;
   a.kahan = precision == IDW_FP32_KAHAN;
+  // Large p in FP32: relative weights, sigma from each query's nearest distance.
+  a.rel = !f64 && p >= kRelP;
+  a.rmin = reinterpret_cast<const unsigned long long*>(ws + w.near_min);
   a.split = w.split_f;
   a.chunk = w.chunk_f;
   a.hdr = reinterpret_cast<const double*>(ws + w.hdr);
@@ -471,14 +493,16 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   a.fpart = reinterpret_cast<double4*>(ws + w.fpart);
 
   const LayoutFns& F = fns(data->layout);
-  if ((rc = check_hip(enqueue_header(data, p, f64, ws, w, st), "extent kernels"))) return rc;
+  const bool excl = (flags & IDW_EXCLUDE_SELF) != 0;
+  if ((rc = check_hip(enqueue_header(data, p, f64, a.rel, ws, w, st), "extent kernels"))) return rc;
+  if (a.rel && (rc = check_hip(nearest_all(F, data, query, excl, ws, w, st), "nearest-distance pass")))
+    return rc;
   if ((rc = check_hip(timed(IDW_T_FWD_SWEEP, st, [&] { return F.fwd_sweep(a, f64, st); }), "forward sweep")))
     return rc;
   if (a.split > 1 &&
       (rc = check_hip(merge_split(a.part, m, a.split, a.hdr, out_z, f64, out_den, a.flag, st), "merge")))
     return rc;
-  if ((rc = check_hip(settle_routes(F, data, query, f64, (flags & IDW_EXCLUDE_SELF) != 0, ws, w, st),
-                      "near-coincidence check")))
+  if ((rc = check_hip(settle_routes(F, data, query, f64, excl, ws, w, st), "near-coincidence check")))
     return rc;
   if ((rc = check_hip(F.fwd_fixup(a, f64, st), "FP64 fix-up"))) return rc;
   return IDW_OK;
@@ -559,7 +583,12 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
 
   const LayoutFns& F = fns(data->layout);
   uint8_t* flag = reinterpret_cast<uint8_t*>(ws + w.flag);
-  if ((rc = check_hip(enqueue_header(data, p, f64, ws, w, st), "extent kernels"))) return rc;
+  // Large p in FP32: the fused sweep with relative weights serves every request (the
+  // separate sweeps, when asked for, keep the direct weights and their FP64 routing).
+  const bool separate = cfg && cfg->separate_adjoint;
+  const bool rel = !f64 && p >= kRelP && !separate && w.fused_groups > 0;
+  a.rel = rel;
+  if ((rc = check_hip(enqueue_header(data, p, f64, rel, ws, w, st), "extent kernels"))) return rc;
   if ((rc = check_hip(flags_from_den(saved_den, m, a.hdr, flag, st), "flags"))) return rc;
   if ((rc = check_hip(settle_routes(F, data, query, f64, (flags & IDW_EXCLUDE_SELF) != 0, ws, w, st),
                       "near-coincidence check")))
@@ -567,8 +596,7 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
   a.route = flag;
   // The fused FP32 sweep pays off when both directions are needed: dz or dx with dp or dq,
   // or dx alone (its per-pair factors are those of dq).
-  const bool fused = !f64 && (ndx || (ndz && (ndp || ndq))) && w.fused_groups > 0 &&
-                     !(cfg && cfg->separate_adjoint);
+  const bool fused = rel || (!f64 && (ndx || (ndz && (ndp || ndq))) && w.fused_groups > 0 && !separate);
   if (fused) {  // one FP32 sweep for dp/dq and dz (and dx)
     a.fused_groups = w.fused_groups;
     a.fused_ranges = w.fused_ranges;

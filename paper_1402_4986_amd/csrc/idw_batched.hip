@@ -111,7 +111,7 @@ __global__ __launch_bounds__(64) void kb_bbox_final(const BInst* __restrict__ in
     ext = fmax(ext, mx - mn);
   }
   for (int b = 0; b < nb; ++b) vm = fmax(vm, rec[b * kBboxStride + 6]);
-  fill_header(hdr + static_cast<int64_t>(i) * kBHdr, ext, vm, I.p, true);
+  fill_header(hdr + static_cast<int64_t>(i) * kBHdr, ext, vm, I.p, true, false);
 }
 
 // ---- persistent sweep ----
@@ -167,12 +167,15 @@ __device__ __forceinline__ void kb_item(const BInst& I, const BItem& it, const d
     }
   };
   const int ntiles = static_cast<int>((je - jb + kTile - 1) / kTile);
+  float one[kBQ];  // direct weights: no per-query scaling
+#pragma unroll
+  for (int k = 0; k < kBQ; ++k) one[k] = 1.f;
   fetch(0);
   put(0);
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) fetch(t + 1);
-    fwd_tile<float, DIM, PM, kBQ, false, 4>(tile[t & 1], 0, qc, qi, I.nhp, nh, nl, dh, dl);
+    fwd_tile<float, DIM, PM, kBQ, false, 4>(tile[t & 1], 0, qc, qi, I.nhp, one, nh, nl, dh, dl);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }

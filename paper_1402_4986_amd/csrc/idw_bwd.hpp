@@ -266,12 +266,22 @@ __global__ __launch_bounds__(kWG) void k_bwd_qmerge(const double4* __restrict__ 
         two_sum_acc(G[1][0], G[1][1], v.z);
         two_sum_acc(G[2][0], G[2][1], v.w);
       }
-      const double Ds = D / hdr[H_DEN_UNIT];  // denominator in the sweep's scaled units
+      double Ds = D / hdr[H_DEN_UNIT];  // denominator in the sweep's scaled units
+      double sig = 1.0;
+      // Relative weights: the sweep's sums are sigma^(-p/2) P and sigma^(-p/2 - 1) G, and
+      // E = Ds sigma^(-p/2) takes the place of Ds.
+      if (hdr[H_REL] != 0.0) {
+        float sg = 1.f, k = 0.f;
+        double E = 1.0;
+        rel_from_den(Ds, p, sg, k, E);
+        Ds = E;
+        sig = static_cast<double>(sg);
+      }
       const double g = static_cast<double>(grad_out[i]);
       // ln(r2) = log2(r2) * ln 2; dZ/dp = -(1/D) sum w (1/2) ln(r2) (z - Z).
       dpi = -(g / Ds) * 0.5 * 0.69314718055994530942 * (P[0] + P[1]);
       if (grad_q) {
-        const double f = -(p * g / Ds) * hdr[H_SCALE];
+        const double f = -(p * g / Ds) * sig * hdr[H_SCALE];
 #pragma unroll
         for (int d = 0; d < DIM; ++d) grad_q[i * DIM + d] = static_cast<T>(f * (G[d][0] + G[d][1]));
       }

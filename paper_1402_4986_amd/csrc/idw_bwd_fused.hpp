@@ -39,12 +39,16 @@ __device__ __forceinline__ float rotate_in(float v) {
 // One 64-point batch.  MASK: some pairs must be skipped (padding records beyond the data
 // range, or the leave-one-out self pair); those get r2 = 1 and zero value factors.
 // Returns the dz running sum; with NDX, ax holds the X running sums.
-template <int DIM, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool MASK, int UNR>
+// REL: relative weights; the squared distance is multiplied by the query's sigma (sg)
+// before the weight terms, log2 r2 = log2(r2 sigma) - k (kq), and the X sums take the
+// coefficient a sigma (axq) so that they stay those of the direct form.
+template <int DIM, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool MASK, int UNR, bool REL = false>
 __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, int lane, int64_t jb,
                                             int64_t je, bool excl, const float (&qc)[Q][3],
                                             const float (&zq)[Q], const float (&aq)[Q],
-                                            const int64_t (&qi)[Q], float nhp, float (&ap)[Q],
-                                            float (&ag)[Q][3], float (&ax)[3]) {
+                                            const float (&sg)[Q], const float (&kq)[Q],
+                                            const float (&axq)[Q], const int64_t (&qi)[Q], float nhp,
+                                            float (&ap)[Q], float (&ag)[Q][3], float (&ax)[3]) {
   float acc = 0.f;
   ax[0] = ax[1] = ax[2] = 0.f;
   const P4<float>* r0 = rec + lane;
@@ -73,15 +77,19 @@ __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, i
       }
       float c = dv - zq[k];
       float a = aq[k];
+      float av = REL ? axq[k] : a;
+      if constexpr (REL) r2 *= sg[k];
       if constexpr (MASK) {
         if (!valid || (excl && j == qi[k])) {
           r2 = 1.f;
           c = 0.f;
           a = 0.f;
+          av = 0.f;
         }
       }
       float w, f = 0.f, lg = 0.f;
       wterms<PM, NDQ || NDX, NDP>(r2, nhp, w, f, lg);
+      if constexpr (REL && NDP) lg -= kq[k];
       const float t = w * c;
       if constexpr (NDP) ap[k] = fmaf(t, lg, ap[k]);
       if constexpr (NDQ || NDX) {
@@ -92,7 +100,7 @@ __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, i
           if constexpr (DIM == 3) ag[k][2] = fmaf(u, dz, ag[k][2]);
         }
         if constexpr (NDX) {
-          const float v = a * u;
+          const float v = av * u;
           sx[0] = (k == 0) ? v * dx : fmaf(v, dx, sx[0]);
           sx[1] = (k == 0) ? v * dy : fmaf(v, dy, sx[1]);
           if constexpr (DIM == 3) sx[2] = (k == 0) ? v * dz : fmaf(v, dz, sx[2]);
@@ -119,12 +127,13 @@ constexpr int kFNT = 512;
 // pair terms finite, so that their zero factors a = 0 give exact zeros.
 constexpr float kFarF = 0x1p60f;
 
-template <int DIM, int L, int PM, int Q, bool NDP, bool NDQ, bool NDX, int UNR = 2, int WPE = 2, int NT = kFNT>
+template <int DIM, int L, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool REL = false, int UNR = 2, int WPE = 2,
+          int NT = kFNT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_fused(
     DevPts data, int64_t n, DevPts query, int64_t m, int64_t chunk, int groups, float nhp, unsigned flags,
     const double* __restrict__ hdr, const float* __restrict__ saved_z, const float* __restrict__ grad_out,
     const double* __restrict__ saved_den, double4* __restrict__ part_q, double* __restrict__ part_z,
-    double* __restrict__ part_x, const uint8_t* __restrict__ route) {
+    double* __restrict__ part_x, const uint8_t* __restrict__ route, double pd) {
   __shared__ P4<float> tile[2][2 * kFTile];   // batches stored twice in a row
   constexpr int PPT = kFTile / NT;            // tile points staged per thread
   __shared__ float zred[NT / 64][kFTile];    // per-wave dz sums of the current tile
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
   int first = 1;
   for (int64_t qb = qg; qb < nqb; qb += groups, first = 0) {
     const int64_t q0 = qb * qpb;
-    float qc[Q][3], zq[Q], aq[Q];
+    float qc[Q][3], zq[Q], aq[Q], sg[Q], kq[Q], axq[Q];
     int64_t qi[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -177,13 +186,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
       bool ok = false;
       zq[k] = 0.f;
       aq[k] = 0.f;
+      sg[k] = 1.f;
+      kq[k] = 0.f;
+      axq[k] = 0.f;
       if (qi[k] < m) {
         ok = route[qi[k]] == F_FP32;  // the others are left to the FP64 fix-up
         if (ok) {
           const double D = saved_den[qi[k]];
           Loader<float, DIM, L>::query(query, qi[k], c);
           zq[k] = saved_z[qi[k]];
-          aq[k] = static_cast<float>(static_cast<double>(grad_out[qi[k]]) / (D / unit));
+          const double g = static_cast<double>(grad_out[qi[k]]);
+          if constexpr (REL) {
+            double E = 1.0;
+            rel_from_den(D / unit, pd, sg[k], kq[k], E);
+            aq[k] = static_cast<float>(g / E);
+            axq[k] = static_cast<float>(g / E * static_cast<double>(sg[k]));
+          } else {
+            aq[k] = static_cast<float>(g / (D / unit));
+          }
         }
       }
 #pragma unroll
@@ -217,11 +237,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
         const int64_t jbat = jt + b * kBatch;
         float zs, ax[3];
         if (diag || tail)
-          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, NDX, true, 1>(rec, lane, jbat, je, excl, qc, zq, aq, qi, nhp,
-                                                             ap, ag, ax);
+          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, NDX, true, 1, REL>(rec, lane, jbat, je, excl, qc, zq, aq, sg, kq,
+                                                                  axq, qi, nhp, ap, ag, ax);
         else
-          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, NDX, false, UNR>(rec, lane, jbat, je, excl, qc, zq, aq, qi,
-                                                                nhp, ap, ag, ax);
+          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, NDX, false, UNR, REL>(rec, lane, jbat, je, excl, qc, zq, aq, sg,
+                                                                     kq, axq, qi, nhp, ap, ag, ax);
         const int at = b * kBatch + ((lane + kBatch - 1) & (kBatch - 1));
         zred[wave][at] = zs;
         if constexpr (NDX) {
@@ -286,33 +306,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
   }
 }
 
-template <int DIM, int L, int PM>
+template <int DIM, int L, int PM, bool REL = false>
 hipError_t launch_bwd_fused_t(const BwdArgs& a, int groups, int ranges, int64_t chunk, hipStream_t st) {
   const bool ndp = (a.flags & 0x4u) != 0, ndq = (a.flags & 0x8u) != 0, ndx = a.part_x != nullptr;
   dim3 grid(static_cast<unsigned>(groups), static_cast<unsigned>(ranges));
   const float nhp = static_cast<float>(-0.5 * a.p);
   const float* sz = static_cast<const float*>(a.saved_z);
   const float* go = static_cast<const float*>(a.grad_out);
-#define IDW_BF(DP, DQ, DX)                                                                          \
-  hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ, DX>), grid, dim3(kFNT), 0, st, a.data, a.n, \
-                     a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den,         \
-                     a.part_q, a.part_z, a.part_x, a.route)
+#define IDW_BF(DP, DQ, DX)                                                                               \
+  hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ, DX, REL>), grid, dim3(kFNT), 0, st, a.data, a.n, \
+                     a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den,              \
+                     a.part_q, a.part_z, a.part_x, a.route, a.p)
   // The data-coordinate gradient is instantiated with both query-direction sums (they share
-  // its per-pair factors); merges write only what was requested.
+  // its per-pair factors); merges write only what was requested.  With relative weights
+  // every request runs here, dz alone included.
   if (ndx)
     IDW_BF(true, true, true);
   else if (ndp && ndq)
     IDW_BF(true, true, false);
   else if (ndp)
     IDW_BF(true, false, false);
-  else
+  else if (ndq)
     IDW_BF(false, true, false);
+  else if constexpr (REL)
+    IDW_BF(false, false, false);
+  else
+    return hipErrorInvalidValue;
 #undef IDW_BF
   return hipGetLastError();
 }
 
 template <int DIM, int L>
 hipError_t bwd_fused_pm(const BwdArgs& a, int groups, int ranges, int64_t chunk, hipStream_t st) {
+  if (a.rel)
+    return a.pmode == PM_GEN ? launch_bwd_fused_t<DIM, L, PM_GEN, true>(a, groups, ranges, chunk, st)
+                             : hipErrorInvalidValue;
   switch (a.pmode) {
     case PM_1: return launch_bwd_fused_t<DIM, L, PM_1>(a, groups, ranges, chunk, st);
     case PM_2: return launch_bwd_fused_t<DIM, L, PM_2>(a, groups, ranges, chunk, st);

@@ -10,7 +10,7 @@ namespace idw {
 
 // Reduces the per-workgroup extent partials and fills the workspace header.
 __global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ part, int nb,
-                                                    int dim, double p, int f32s,
+                                                    int dim, double p, int f32s, int rel,
                                                     double* __restrict__ hdr) {
   __shared__ double red[kWG];
   const int t = threadIdx.x;
@@ -44,13 +44,13 @@ __global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ p
     if (t < s) red[t] = fmax(red[t], red[t + s]);
     __syncthreads();
   }
-  if (t == 0) fill_header(hdr, ext, red[0], p, f32s != 0);
+  if (t == 0) fill_header(hdr, ext, red[0], p, f32s != 0, rel != 0);
 }
 
 hipError_t bbox_final(const double* part, int nblocks, int dim, double p, bool f32_scaling,
-                      double* hdr, hipStream_t st) {
+                      bool rel, double* hdr, hipStream_t st) {
   hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kWG), 0, st, part, nblocks, dim, p,
-                     f32_scaling ? 1 : 0, hdr);
+                     f32_scaling ? 1 : 0, rel ? 1 : 0, hdr);
   return hipGetLastError();
 }
 

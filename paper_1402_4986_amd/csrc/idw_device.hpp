@@ -276,8 +276,47 @@ enum HdrSlot {
   H_GEO_S = 8,     // near-coincidence threshold on the denominator, scaled units
   H_GEO_U = 9,     // near-coincidence threshold, caller units
   H_NEAR_R2 = 10,  // squared near-coincidence distance (1e-6 extent s)^2, scaled units
+  H_REL = 11,      // 1 when the FP32 sweeps use per-query relative weights (large p), else 0
   H_COUNT_I = 32   // int slots start at byte 256: [0] flagged count
 };
+
+// From this exponent on the FP32 sweeps use relative weights: a query's weights are taken
+// relative to a power of two near its largest one, w' = (r2 sigma)^(-p/2) = w sigma^(-p/2)
+// with sigma = 2^k chosen per query, so that no weight of Eq. 1 has to fit the FP32 range
+// by itself.  (With the direct weights, 1M uniform points at p = 6 already put about one
+// query in eight past the FP32-safe bound and into the FP64 recomputation, which then
+// costs more than the relative form's nearest-distance pass.)  The forward takes sigma from the query's nearest squared distance (r2min
+// sigma in [1/2, 1), so 1 < w'max <= 2^(p/2)); the adjoint takes it from the saved
+// denominator (relative denominator E = D / sigma^(p/2) in [1, 2^(p/2))).  Because the
+// nearest pairs then have r2 sigma close to 1, the weight's log2 / exp2 evaluation keeps
+// about the accuracy it has at small p.
+constexpr double kRelP = 6.0;
+constexpr double kRelVmax = 4294967296.0;  // 2^32: largest |value| the relative sweeps take
+
+// Adjoint scaling of one query from its denominator Ds (scaled units, finite, > 0):
+// sigma = 2^k with k = floor((2/p) log2 Ds) (clamped to the normal FP32 range), E =
+// Ds sigma^(-p/2) in [1, 2^(p/2)), and k itself (for log2 r2 = log2(r2 sigma) - k).
+__device__ inline void rel_from_den(double Ds, double p, float& sig, float& k, double& E) {
+  double kk = floor((2.0 / p) * log2(Ds));
+  kk = fmin(fmax(kk, -125.0), 125.0);
+  sig = __builtin_amdgcn_ldexpf(1.0f, static_cast<int>(kk));
+  k = static_cast<float>(kk);
+  E = Ds * exp2(-0.5 * p * kk);
+}
+
+// Forward scaling of one query from its nearest squared distance r2min (FP32, scaled
+// units): sigma = 2^-e where r2min = m 2^e, m in [1/2, 1), so r2min sigma = m; the sweep's
+// sums are multiplied by F = sigma^(p/2) (FP64) to give scaled-unit sums.  A zero,
+// subnormal or non-finite r2min (the query is routed to the FP64 fix-up by its
+// denominator) gets sigma = 1 when infinite and the clamped exponent otherwise.
+__device__ inline void rel_from_min(float r2min, double p, float& sig, double& F) {
+  int e = 0;
+  if (r2min > 0.0f && r2min < __builtin_huge_valf()) e = __builtin_amdgcn_frexp_expf(r2min);
+  if (r2min == 0.0f) e = -125;
+  e = e < -125 ? -125 : (e > 125 ? 125 : e);
+  sig = __builtin_amdgcn_ldexpf(1.0f, -e);
+  F = exp2(-0.5 * p * static_cast<double>(e));
+}
 
 // Per-query route after a sweep (flag bytes):
 //  F_FP32       the sweep's result stands;
@@ -315,8 +354,13 @@ constexpr int kBboxStride = 8;
 //  least 2^-21 (scaled units), which bounds every FP32 term and sum of the forward and
 //  adjoint sweeps below 2^125.  Thresholds are finite: for large p, (1e-6 * extent)^-p
 //  overflows, and an infinite threshold would pass an infinite denominator.
+//  Relative weights (rel, FP32 with p >= kRelP): no weight is held in FP32 by itself, so the
+//  cap becomes the value bound alone (every query goes to FP64 when max|value| > kRelVmax),
+//  and the lower threshold is 2^(-10 p) (scaled units): a denominator above it has its
+//  nearest squared distance below 2^20 n^(2/p), which keeps the adjoint's sigma above
+//  2^-21 and its distance factors finite; farther queries are recomputed in FP64.
 __device__ inline void fill_header(double* __restrict__ h, double ext, double vmax, double p,
-                                   bool f32s) {
+                                   bool f32s, bool rel) {
   if (!(ext > 0.0) || !(ext < __builtin_huge_val())) ext = 1.0;
   double s = 1.0;
   double cap_s = __DBL_MAX__;
@@ -327,6 +371,10 @@ __device__ inline void fill_header(double* __restrict__ h, double ext, double vm
     s = ldexp(1.0, -e);
     cap_s = ldexp(1.0, 80) / fmax(1.0, vmax);
     lo_s = ldexp(1.0, -60);
+    if (rel) {
+      cap_s = vmax <= kRelVmax ? __DBL_MAX__ : -1.0;
+      lo_s = exp2(-10.0 * p);
+    }
   }
   const double near = 1e-6 * ext * s;
   const double geo_s = fmin(pow(near, -p), __DBL_MAX__);
@@ -342,6 +390,7 @@ __device__ inline void fill_header(double* __restrict__ h, double ext, double vm
   h[H_GEO_S] = geo_s;
   h[H_GEO_U] = fmin(geo_s * unit, __DBL_MAX__);
   h[H_NEAR_R2] = near * near;
+  h[H_REL] = (f32s && rel) ? 1.0 : 0.0;
 }
 
 }  // namespace idw

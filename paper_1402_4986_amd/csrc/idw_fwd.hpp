@@ -74,10 +74,13 @@ __device__ __forceinline__ void kahan_add(T& s, T& e, T x) {
 // KH = false: plain sums over 64-record blocks, each merged into (hi, lo) by TwoSum.
 // KH = true: Kahan-compensated update of (hi, lo) on every pair (about 3 more VALU
 // operations per accumulator and pair; the accuracy variant).
-template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR, bool KH = false>
+// REL = true: relative weights, the squared distance multiplied by the query's sigma
+// before the weight is taken (one more multiply per pair).
+template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR, bool KH = false, bool REL = false>
 __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t jt,
                                          const T (&qc)[Q][3], const int64_t (&qi)[Q], T nhp,
-                                         T (&nh)[Q], T (&nl)[Q], T (&dh)[Q], T (&dl)[Q]) {
+                                         const T (&sg)[Q], T (&nh)[Q], T (&nl)[Q], T (&dh)[Q],
+                                         T (&dl)[Q]) {
   constexpr int CH = 64;
   if constexpr (KH) {
 #pragma unroll UNR
@@ -86,7 +89,8 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
       const T dv = (DIM == 3) ? d.w : d.z;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        const T r2 = sqdist<T, DIM>(qc[k], d);
+        T r2 = sqdist<T, DIM>(qc[k], d);
+        if constexpr (REL) r2 *= sg[k];
         T w = weight<PM>(r2, nhp);
         if constexpr (DIAG) {
           if (jt + jj == qi[k]) w = T(0);
@@ -110,7 +114,8 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
       const T dv = (DIM == 3) ? d.w : d.z;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        const T r2 = sqdist<T, DIM>(qc[k], d);
+        T r2 = sqdist<T, DIM>(qc[k], d);
+        if constexpr (REL) r2 *= sg[k];
         T w = weight<PM>(r2, nhp);
         if constexpr (DIAG) {
           if (jt + c0 + jj == qi[k]) w = T(0);
@@ -147,15 +152,20 @@ struct SweepTune {
   static constexpr int WPE = 1;
 };
 
+// REL: relative weights; rmin holds each query's nearest squared distance (FP32 bits,
+// scaled units, from k_near_check over all queries) and the sums leave the kernel
+// multiplied by sigma^(p/2), i.e. in scaled units like those of the direct form.
 template <typename T, int DIM, int L, int PM, int Q, int UNR = SweepTune<T, Q>::UNR,
-          int WPE = SweepTune<T, Q>::WPE, bool KH = false>
+          int WPE = SweepTune<T, Q>::WPE, bool KH = false, bool REL = false>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_fwd_sweep(DevPts data, int64_t n, DevPts query, int64_t m,
                                                    int64_t chunk, int split, T nhp, unsigned flags,
                                                    const double* __restrict__ hdr,
                                                    T* __restrict__ out_z,
                                                    double* __restrict__ out_den,
                                                    uint8_t* __restrict__ out_flag,
-                                                   double2* __restrict__ part) {
+                                                   double2* __restrict__ part,
+                                                   const unsigned long long* __restrict__ rmin,
+                                                   double p) {
   __shared__ P4<T> tile[2][kTile];
   const int tid = threadIdx.x;
   const int64_t q0 = static_cast<int64_t>(blockIdx.x) * (kWG * Q);
@@ -163,13 +173,24 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
   const int64_t je = (jb + chunk < n) ? jb + chunk : n;
   const T s = static_cast<T>(hdr[H_SCALE]);
 
-  T qc[Q][3];
+  T qc[Q][3], sg[Q];
+  double fs[Q];
   int64_t qi[Q];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     qi[k] = q0 + tid + static_cast<int64_t>(k) * kWG;
     T c[3] = {T(0), T(0), T(0)};
-    if (qi[k] < m) Loader<T, DIM, L>::query(query, qi[k], c);
+    sg[k] = T(1);
+    fs[k] = 1.0;
+    if (qi[k] < m) {
+      Loader<T, DIM, L>::query(query, qi[k], c);
+      if constexpr (REL) {
+        float sgf = 1.0f;
+        rel_from_min(__builtin_bit_cast(float, static_cast<unsigned int>(rmin[qi[k]])), p, sgf,
+                     fs[k]);
+        sg[k] = static_cast<T>(sgf);
+      }
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) qc[k][d] = c[d] * s;
   }
@@ -205,9 +226,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
     const int64_t jt = jb + static_cast<int64_t>(t) * kTile;
     const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
     if (diag)
-      fwd_tile<T, DIM, PM, Q, true, 1, KH>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
+      fwd_tile<T, DIM, PM, Q, true, 1, KH, REL>(tile[t & 1], jt, qc, qi, nhp, sg, nh, nl, dh, dl);
     else
-      fwd_tile<T, DIM, PM, Q, false, UNR, KH>(tile[t & 1], jt, qc, qi, nhp, nh, nl, dh, dl);
+      fwd_tile<T, DIM, PM, Q, false, UNR, KH, REL>(tile[t & 1], jt, qc, qi, nhp, sg, nh, nl, dh, dl);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }
@@ -215,8 +236,12 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     if (qi[k] < m) {
-      const double num = static_cast<double>(nh[k]) + static_cast<double>(nl[k]);
-      const double den = static_cast<double>(dh[k]) + static_cast<double>(dl[k]);
+      double num = static_cast<double>(nh[k]) + static_cast<double>(nl[k]);
+      double den = static_cast<double>(dh[k]) + static_cast<double>(dl[k]);
+      if constexpr (REL) {
+        num *= fs[k];
+        den *= fs[k];
+      }
       if (split == 1)
         fwd_finish<T>(qi[k], num, den, hdr, out_z, out_den, out_flag);
       else
@@ -256,11 +281,15 @@ __device__ __forceinline__ T from_min_bits(unsigned long long b) {
     return __builtin_bit_cast(double, b);
 }
 
+// With list == nullptr every query 0..mall-1 takes part (the relative-weight forward needs
+// the nearest distance of each query); otherwise the *count queries of list.
 template <typename T>
 __global__ __launch_bounds__(kWG) void k_near_init(const int* __restrict__ list, const int* __restrict__ count,
-                                                   unsigned long long* __restrict__ minb) {
-  const int cnt = *count;
-  for (int i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) minb[list[i]] = min_bits(infT<T>());
+                                                   int64_t mall, unsigned long long* __restrict__ minb) {
+  const int64_t cnt = list ? static_cast<int64_t>(*count) : mall;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; i < cnt;
+       i += static_cast<int64_t>(gridDim.x) * kWG)
+    minb[list ? list[i] : i] = min_bits(infT<T>());
 }
 
 template <typename T>
@@ -278,11 +307,11 @@ __global__ __launch_bounds__(kWG) void k_near_finish(const int* __restrict__ lis
 template <typename T, int DIM, int L, int Q, bool EXCL>
 __global__ __launch_bounds__(kWG) void k_near_check(DevPts data, int64_t n, DevPts query,
                                                     const int* __restrict__ list,
-                                                    const int* __restrict__ count,
+                                                    const int* __restrict__ count, int64_t mall,
                                                     const double* __restrict__ hdr,
                                                     unsigned long long* __restrict__ minb) {
   __shared__ P4<T> tile[2][kTile];
-  const int64_t cnt = *count;
+  const int64_t cnt = list ? static_cast<int64_t>(*count) : mall;
   const int tid = threadIdx.x;
   const T s = static_cast<T>(hdr[H_SCALE]);
   constexpr int64_t kQB = static_cast<int64_t>(kWG) * Q;
@@ -305,7 +334,7 @@ __global__ __launch_bounds__(kWG) void k_near_check(DevPts data, int64_t n, DevP
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       const int64_t slot = b0 + tid + static_cast<int64_t>(k) * kWG;
-      qi[k] = slot < cnt ? list[slot] : -1;
+      qi[k] = slot < cnt ? (list ? list[slot] : slot) : -1;
       T c[3] = {T(0), T(0), T(0)};
       if (qi[k] >= 0) Loader<T, DIM, L>::query(query, qi[k], c);
 #pragma unroll
@@ -510,18 +539,41 @@ hipError_t launch_fwd_sweep_q(const FwdArgs& a, hipStream_t st) {
   dim3 grid(static_cast<unsigned>((a.m + qpb - 1) / qpb), static_cast<unsigned>(a.split));
   const T nhp = static_cast<T>(-0.5 * a.p);
   T* z = static_cast<T*>(a.out_z);
+#define IDW_FWD_ARGS                                                                          \
+  a.data, a.n, a.query, a.m, a.chunk, a.split, nhp, a.flags, a.hdr, z, a.out_den, a.flag, a.part, \
+      a.rmin, a.p
 #define IDW_FWD_Q(QQ)                                                                       \
   case QQ:                                                                                  \
-    hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, QQ>), grid, dim3(kWG), 0, st, a.data,   \
-                       a.n, a.query, a.m, a.chunk, a.split, nhp, a.flags, a.hdr, z,         \
-                       a.out_den, a.flag, a.part);                                          \
+    hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, QQ>), grid, dim3(kWG), 0, st, IDW_FWD_ARGS); \
     break;
   if constexpr (sizeof(T) == 4) {
+    using K4 = SweepTune<T, 4>;
+    using K8 = SweepTune<T, 8>;
+    if (a.rel) {  // relative weights: general-p form only
+      if constexpr (PM == PM_GEN) {
+        if (!a.rmin) return hipErrorInvalidValue;
+        if (a.kahan) {
+          if (Q != 4) return hipErrorInvalidValue;
+          hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, K4::UNR, K4::WPE, true, true>), grid, dim3(kWG), 0, st,
+                             IDW_FWD_ARGS);
+        } else if (Q == 4) {
+          hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, K4::UNR, K4::WPE, false, true>), grid, dim3(kWG), 0,
+                             st, IDW_FWD_ARGS);
+        } else if (Q == 8) {
+          hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 8, K8::UNR, K8::WPE, false, true>), grid, dim3(kWG), 0,
+                             st, IDW_FWD_ARGS);
+        } else {
+          return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
     if (a.kahan) {  // per-pair Kahan variant, 4 queries per lane
       if (Q != 4) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, SweepTune<T, 4>::UNR, SweepTune<T, 4>::WPE, true>), grid,
-                         dim3(kWG), 0, st, a.data, a.n, a.query, a.m, a.chunk, a.split, nhp, a.flags, a.hdr, z,
-                         a.out_den, a.flag, a.part);
+      hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, K4::UNR, K4::WPE, true>), grid, dim3(kWG), 0, st,
+                         IDW_FWD_ARGS);
       return hipGetLastError();
     }
     switch (Q) {
@@ -539,6 +591,7 @@ hipError_t launch_fwd_sweep_q(const FwdArgs& a, hipStream_t st) {
     }
   }
 #undef IDW_FWD_Q
+#undef IDW_FWD_ARGS
   return hipGetLastError();
 }
 
@@ -592,14 +645,17 @@ template <typename T, int DIM, int L>
 hipError_t launch_near_check_t(const NearArgs& a, hipStream_t st) {
   constexpr int Q = sizeof(T) == 4 ? 4 : 2;
   const unsigned gl = static_cast<unsigned>(a.m < 64 * kWG ? (a.m + kWG - 1) / kWG + 1 : 64);
-  hipLaunchKernelGGL((k_near_init<T>), dim3(gl), dim3(kWG), 0, st, a.list, a.count, a.minb);
+  const int* list = a.all ? nullptr : a.list;
+  if (!a.all && !a.list) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_near_init<T>), dim3(gl), dim3(kWG), 0, st, list, a.count, a.m, a.minb);
   if (a.excl)
     hipLaunchKernelGGL((k_near_check<T, DIM, L, Q, true>), dim3(kNearGrid), dim3(kWG), 0, st, a.data, a.n,
-                       a.query, a.list, a.count, a.hdr, a.minb);
+                       a.query, list, a.count, a.m, a.hdr, a.minb);
   else
     hipLaunchKernelGGL((k_near_check<T, DIM, L, Q, false>), dim3(kNearGrid), dim3(kWG), 0, st, a.data, a.n,
-                       a.query, a.list, a.count, a.hdr, a.minb);
-  hipLaunchKernelGGL((k_near_finish<T>), dim3(gl), dim3(kWG), 0, st, a.list, a.count, a.minb, a.hdr, a.route);
+                       a.query, list, a.count, a.m, a.hdr, a.minb);
+  if (!a.all)
+    hipLaunchKernelGGL((k_near_finish<T>), dim3(gl), dim3(kWG), 0, st, a.list, a.count, a.minb, a.hdr, a.route);
   return hipGetLastError();
 }
 

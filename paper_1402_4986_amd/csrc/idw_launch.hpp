@@ -20,6 +20,8 @@ struct FwdArgs {
   unsigned flags = 0;
   int q_per_lane = 8;
   bool kahan = false;  // FP32 sweep with per-pair Kahan compensation
+  bool rel = false;    // FP32 relative weights (p >= kRelP): needs rmin
+  const unsigned long long* rmin = nullptr;  // [m] nearest squared distance (FP32 bits)
   int split = 1;
   int64_t chunk = 0;  // data points per split chunk (multiple of the tile)
   const double* hdr = nullptr;
@@ -60,6 +62,7 @@ struct BwdArgs {
   const void* saved_z = nullptr;
   const double* saved_den = nullptr;
   const uint8_t* route = nullptr;  // [m] settled QueryRoute of each query
+  bool rel = false;                // fused FP32 sweep with relative weights (p >= kRelP)
   void* grad_z = nullptr;
   void* grad_q = nullptr;
   void* grad_x = nullptr;
@@ -89,6 +92,7 @@ struct NearArgs {
   const double* hdr = nullptr;
   uint8_t* route = nullptr;    // [m] QueryRoute, settled for the candidates
   unsigned long long* minb = nullptr;  // [m] per-candidate minimum (bits), scratch
+  bool all = false;  // every query 0..m-1 (list and count unused); no route is written
 };
 
 constexpr int kTile = 512;        // data points staged in LDS per tile (2 per thread)
@@ -116,7 +120,7 @@ IDW_DECLARE_LAYOUT(soaos)
 
 // Layout-independent kernels (idw_common.hip).
 hipError_t bbox_final(const double* part, int nblocks, int dim, double p, bool f32_scaling,
-                      double* hdr, hipStream_t st);
+                      bool rel, double* hdr, hipStream_t st);
 hipError_t merge_split(const double2* part, int64_t m, int split, const double* hdr,
                        void* out_z, bool f64, double* out_den, uint8_t* flag, hipStream_t st);
 hipError_t compact_flags(const uint8_t* flag, int64_t m, int* bcnt, int* list, int* count,

@@ -1,0 +1,274 @@
+"""FP32 parity for large exponents p (p >= 6), where the FP32 sweeps use relative weights.
+
+A data point at distance d has weight d^-p; at p = 8 and 1M uniform points the nearest
+weights already pass the FP32-safe bound, and at p = 64 nearly every weight of Eq. 1 lies
+outside the FP32 range.  From p = 6 on the FP32 sweeps therefore take each query's weights
+relative to a power of two near its largest one (sigma from the query's nearest distance in
+the forward, from its saved denominator in the adjoint), so the queries stay on the FP32
+path instead of the FP64 recomputation.  Each case checks the results against the FP64
+oracle and, through the workspace header (the int at byte 256 holds the number of queries
+the last call routed to FP64), that the FP32 path did the work.
+
+Tolerances: 1e-5 relative to the condition scales, as at small p.  In the relative sweeps
+a weight below FLT_MIN of its query's scale may be flushed to zero; a value gradient dz_j
+then loses at most |g_i| 2^-126 per query (the relative denominator is at least 1), which
+is the absolute floor of dz here (2^-126 sum |g|).  dx_j has the same terms times
+p |z_j - Z_i| |q_i - x_j| / r2, bounded below by the floor used for it.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import GTOL, TOL, points, rand_case, scaled_err
+from paper_1402_4986_amd import api
+
+pytestmark = pytest.mark.gpu
+
+
+def _fp64_count(ws):
+    torch.cuda.synchronize()
+    return int(ws[256:260].view(torch.int32).item())
+
+
+def _case(seed, n, m, dim, hits=6, near=4):
+    x, z, q = rand_case(seed, n, m, dim)
+    q[:hits] = x[:hits]                                            # exact hits
+    q[hits:hits + near] = x[200:200 + near] + 3e-8                 # within 1e-6 of the extent
+    return x, z, q.astype(np.float32).astype(np.float64)
+
+
+def _forward(x, z, q, p, layout, prec="f32", **kw):
+    d, qq = points(x, z, q, layout, prec)
+    cfg = api._cfg(kw.get("queries_per_lane", 0), kw.get("split", 0))
+    ws = api.workspace(d, qq, prec, cfg, backward=False)
+    Z, D = api.forward(d, qq, p, prec, ws=ws, **kw)
+    torch.cuda.synchronize()
+    return Z.cpu().numpy().astype(np.float64), D.cpu().numpy(), _fp64_count(ws)
+
+
+def _check_forward(Z, D, ref, skip):
+    assert np.all(np.isfinite(Z))
+    assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
+    ok = np.isfinite(ref["D"])
+    ok[:skip] = False
+    assert np.max(np.abs(D[ok] - ref["D"][ok]) / ref["D"][ok]) <= 1e-5
+
+
+@pytest.mark.parametrize("p", [6.0, 8.0, 12.5, 24.0, 40.0, 64.0])
+@pytest.mark.parametrize("dim,layout", [(2, "soa"), (3, "aoas")])
+def test_forward_large_p(p, dim, layout):
+    # Near-coincident queries only where the oracle's own weights stay finite.
+    near = 4 if p <= 24.0 else 0
+    x, z, q = _case(1000 + dim, 4000, 1500, dim, near=near)
+    print(f"case p={p} dim={dim} layout={layout}", flush=True)
+    ref = oracle.forward(x, z, q, p)
+    assert np.all(np.isfinite(ref["Z"]))
+    Z, D, nf = _forward(x, z, q, p, layout)
+    _check_forward(Z, D, ref, 6 + near)
+    np.testing.assert_array_equal(Z[:6], ref["Z"][:6].astype(np.float32))
+    assert nf == 6 + near, f"{nf} queries went to FP64"
+
+
+def test_forward_large_p_kahan_and_split():
+    x, z, q = _case(1010, 6000, 2000, 2)
+    p = 16.0
+    ref = oracle.forward(x, z, q, p)
+    for kw in ({"prec": "f32_kahan"}, {"split": 7}, {"queries_per_lane": 8}):
+        print(f"case {kw}", flush=True)
+        Z, D, nf = _forward(x, z, q, p, "aoas", **kw)
+        _check_forward(Z, D, ref, 10)
+        assert nf == 10
+
+
+def test_forward_large_p_far_queries():
+    # Queries 10 and 10^4 extents away: the former stay on the FP32 path, the latter (their
+    # denominators below 2^(-10 p) in scaled units) are recomputed in FP64.
+    x, z, q = _case(1020, 3000, 400, 2, hits=0, near=0)
+    q[:100] += 10.0
+    q[100:200] += 1e4
+    q = q.astype(np.float32).astype(np.float64)
+    p = 20.0
+    ref = oracle.forward(x, z, q, p)
+    Z, D, nf = _forward(x, z, q, p, "hybrid")
+    _check_forward(Z, D, ref, 0)
+    assert nf == 100
+
+
+def test_forward_large_p_huge_values_go_to_fp64():
+    # max |z| above 2^32: the relative sweeps do not take it, every query is recomputed.
+    x, z, q = _case(1030, 2000, 300, 2, hits=2, near=0)
+    z = (z * 1e12).astype(np.float32).astype(np.float64)
+    ref = oracle.forward(x, z, q, 10.0)
+    Z, D, nf = _forward(x, z, q, 10.0, "aos")
+    _check_forward(Z, D, ref, 2)
+    assert nf == len(q)
+
+
+def _floors(g, p, x, z, q):
+    fz = 2.0 ** -126 * np.sum(np.abs(g)) + 2.0 ** -149
+    ext = np.max(np.ptp(x, axis=0))
+    fx = fz * p * 2 * np.max(np.abs(z)) * 2 ** 21 / ext
+    return fz, fx
+
+
+def _adjoint(x, z, q, p, layout, g, need=(True, True, True, True), exclude_self=False, separate=False):
+    d, qq = points(x, z, q, layout, "f32")
+    ws = api.workspace(d, qq, "f32", need_dx=need[3])
+    Z, D = api.forward(d, qq, p, "f32", exclude_self=exclude_self, ws=ws)
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda")
+    out = api.backward(d, qq, p, gt, Z, D, "f32", need_dz=need[0], need_dp=need[1], need_dq=need[2],
+                       need_dx=need[3], exclude_self=exclude_self, separate=separate, ws=ws)
+    nf = _fp64_count(ws)
+    host = []
+    for o in out:
+        if o is None:
+            host.append(None)
+        elif o.numel() == 1 and o.dtype == torch.float64:
+            host.append(float(o))
+        else:
+            host.append(o.cpu().numpy().astype(np.float64))
+    if len(host) == 3:
+        host.append(None)
+    return host, nf
+
+
+def _check_adjoint(got, ref, refx, floors, need=(True, True, True, True)):
+    tol = GTOL["f32"]
+    fz, fx = floors
+    dz, dp, dq = got[0], got[1], got[2]
+    if need[0]:
+        e = np.abs(dz - ref["dz"]) - tol * ref["dz_scale"]
+        assert np.max(e) <= fz, f"dz err {np.max(e):.3e}"
+    if need[1]:
+        assert abs(dp - ref["dp"]) <= tol * ref["dp_cond"], f"dp {dp} vs {ref['dp']}"
+    if need[2]:
+        e = np.max(np.abs(dq - ref["dq"]), axis=1) / np.maximum(ref["dq_cond"], 1e-300)
+        assert np.max(e) <= tol, f"dq err {np.max(e):.3e}"
+    if need[3]:
+        dx = got[3]
+        e = np.max(np.abs(dx - refx["dx"]), axis=1) - tol * refx["dx_cond"]
+        assert np.max(e) <= fx, f"dx err {np.max(e):.3e}"
+
+
+@pytest.mark.parametrize("p", [8.0, 17.5, 40.0])
+@pytest.mark.parametrize("dim,layout", [(2, "aoas"), (3, "soa")])
+def test_adjoint_large_p(p, dim, layout):
+    x, z, q = _case(1100 + dim, 3000, 1200, dim, near=4 if p <= 24 else 0)
+    g = np.random.default_rng(1101).normal(size=len(q)).astype(np.float32).astype(np.float64)
+    print(f"case p={p} dim={dim} layout={layout}", flush=True)
+    got, nf = _adjoint(x, z, q, p, layout, g)
+    ref = oracle.backward(x, z, q, p, g)
+    refx = oracle.backward_x(x, z, q, p, g)
+    _check_adjoint(got, ref, refx, _floors(g, p, x, z, q))
+    assert nf == (10 if p <= 24 else 6)
+
+
+@pytest.mark.parametrize("need", [(True, False, False, False), (False, True, False, False),
+                                  (False, False, True, False), (False, False, False, True),
+                                  (True, True, True, False)])
+def test_adjoint_large_p_single_requests(need):
+    x, z, q = _case(1110, 2500, 900, 2)
+    g = np.random.default_rng(1111).normal(size=len(q)).astype(np.float32).astype(np.float64)
+    p = 10.0
+    print(f"case need={need}", flush=True)
+    got, nf = _adjoint(x, z, q, p, "hybrid", g, need=need)
+    ref = oracle.backward(x, z, q, p, g)
+    refx = oracle.backward_x(x, z, q, p, g) if need[3] else None
+    for k in range(4):
+        assert (got[k] is None) != need[k]
+    _check_adjoint(got, ref, refx, _floors(g, p, x, z, q), need)
+    assert nf == 10
+
+
+def test_adjoint_large_p_separate_sweeps():
+    # The separate sweeps keep the direct weights: queries past the FP32 cap are recomputed
+    # in FP64, and the results agree with the oracle all the same.
+    x, z, q = _case(1120, 2500, 900, 2)
+    g = np.random.default_rng(1121).normal(size=len(q)).astype(np.float32).astype(np.float64)
+    p = 12.0
+    got, _ = _adjoint(x, z, q, p, "aoas", g, need=(True, True, True, False), separate=True)
+    ref = oracle.backward(x, z, q, p, g)
+    _check_adjoint(got, ref, None, _floors(g, p, x, z, q), (True, True, True, False))
+
+
+def test_leave_one_out_large_p():
+    x, z, _ = rand_case(1130, 4000, 1, 2)
+    p = 9.0
+    g = np.random.default_rng(1131).normal(size=len(x)).astype(np.float32).astype(np.float64)
+    idx = np.arange(len(x))
+    Z, D, nf = _forward(x, z, x, p, "hybrid", exclude_self=True)
+    ref = oracle.forward(x, z, x, p, self_index=idx)
+    _check_forward(Z, D, ref, 0)
+    assert nf == 0
+    got, _ = _adjoint(x, z, x, p, "hybrid", g, need=(True, True, False, False), exclude_self=True)
+    refb = oracle.backward(x, z, x, p, g, self_index=idx)
+    _check_adjoint(got, refb, None, _floors(g, p, x, z, x), (True, True, False, False))
+
+
+def test_large_p_graph_replay_bitwise():
+    x, z, q = _case(1140, 3000, 1200, 2)
+    d, qq = points(x, z, q, "aoas", "f32")
+    g = torch.as_tensor(np.random.default_rng(1141).normal(size=len(q)), dtype=torch.float32, device="cuda")
+    ws = api.workspace(d, qq, "f32", need_dx=True)
+    Z = torch.empty(len(q), dtype=torch.float32, device="cuda")
+    D = torch.empty(len(q), dtype=torch.float64, device="cuda")
+
+    def step():
+        api.forward(d, qq, 12.0, "f32", out_z=Z, out_den=D, ws=ws)
+        return api.backward(d, qq, 12.0, g, Z, D, "f32", ws=ws, need_dx=True)
+
+    eager = [a.clone() for a in step()]
+    eager_z = Z.clone()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = step()
+    for rep in range(3):
+        Z.fill_(float("nan"))
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        print(f"replay {rep}", flush=True)
+        assert torch.equal(Z, eager_z)
+        for a, b in zip(outs, eager):
+            assert torch.equal(a, b)
+
+
+def test_large_p_million_points_sampled():
+    # 1,048,576 data points at p = 8 (the nearest weights pass the direct FP32 bound):
+    # sampled forward queries against the oracle, and an adjoint whose upstream gradient
+    # is non-zero on 120 queries only, so the oracle needs just those.
+    x, z, q = rand_case(1150, 1 << 20, 4096, 2)
+    p = 8.0
+    d, qq = points(x, z, q, "aoas", "f32")
+    ws = api.workspace(d, qq, "f32")
+    Z, D = api.forward(d, qq, p, "f32", ws=ws)
+    nf = _fp64_count(ws)
+    assert nf <= 2, f"{nf} queries went to FP64"
+    r = np.random.default_rng(1151)
+    sel = np.sort(r.choice(len(q), size=120, replace=False))
+    ref = oracle.forward(x, z, q[sel], p)
+    Zh = Z.cpu().numpy().astype(np.float64)
+    assert np.max(scaled_err(Zh[sel], ref)) <= TOL["f32"]
+    g = np.zeros(len(q))
+    g[sel] = r.normal(size=len(sel)).astype(np.float32)
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda")
+    dz, dp, dq = api.backward(d, qq, p, gt, Z, D, "f32", ws=ws)
+    torch.cuda.synchronize()
+    rb = oracle.backward(x, z, q[sel], p, g[sel])
+    fz, _ = _floors(g, p, x, z, q)
+    e = np.abs(dz.cpu().numpy().astype(np.float64) - rb["dz"]) - GTOL["f32"] * rb["dz_scale"]
+    assert np.max(e) <= fz
+    assert abs(float(dp) - rb["dp"]) <= GTOL["f32"] * rb["dp_cond"]
+    dqh = dq.cpu().numpy().astype(np.float64)[sel]
+    e = np.max(np.abs(dqh - rb["dq"]), axis=1) / np.maximum(rb["dq_cond"], 1e-300)
+    assert np.max(e) <= GTOL["f32"]

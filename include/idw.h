@@ -40,7 +40,7 @@
  *    [1/2, 1) (no data point within about 2^10 extents).  A weight below FLT_MIN relative
  *    to its query's largest may be flushed to zero: a value gradient dL/dz_j can lose up
  *    to |g_i| 2^-126 per query i.  With separate_adjoint = 1 the adjoint keeps the direct
- *    weights and their FP64 routing.
+ *    weights and their FP64 routing.  Batched plans use the relative weights too.
  */
 #ifndef IDW_H
 #define IDW_H
@@ -219,7 +219,9 @@ typedef struct idw_plan idw_plan;
  * name must stay valid while the plan is used).  Precision IDW_FP32 only; every instance
  * uses the IDW_AOAS layout for data and queries, has its own dim (2 or 3), p (any valid
  * p; 1, 2 and 3 have fast forms) and sizes.  The sweep is the FP32 sweep of idw_forward
- * with its FP64 ratio and FP64 fix-up of near-coincident queries.  The plan allocates its
+ * with its FP64 ratio and FP64 fix-up of near-coincident queries; instances with p >= 6
+ * use its relative weights (a nearest-distance pass over their work items comes first,
+ * see "Large p in FP32" above).  The plan allocates its
  * device work list here (the only allocating entry point) and captures a HIP graph on
  * the first idw_batched call for a given workspace.  `cfg` may be NULL. */
 int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_t precision,

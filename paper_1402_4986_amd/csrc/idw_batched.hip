@@ -10,6 +10,9 @@
 // Each item runs the same LDS-tiled FP32 sweep as idw_forward, dispatched on the
 // instance's dimension and weight class.  A merge kernel finalises every query (FP64
 // ratio, flags), flagged queries are compacted in order and recomputed in FP64.
+// Instances with p >= 6 use relative weights as idw_forward does: a first pass over their
+// work items finds every query's nearest squared distance (integer atomic min on the bits
+// of the non-negative float, order-independent), and their sweep items scale by it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,6 +40,7 @@ struct BInst {
   int split;
   int dim;
   int pmode;
+  int rel;           // relative weights (FP32, p >= kRelP)
   float nhp;         // -p/2
   double p;
 };
@@ -111,13 +115,93 @@ __global__ __launch_bounds__(64) void kb_bbox_final(const BInst* __restrict__ in
     ext = fmax(ext, mx - mn);
   }
   for (int b = 0; b < nb; ++b) vm = fmax(vm, rec[b * kBboxStride + 6]);
-  fill_header(hdr + static_cast<int64_t>(i) * kBHdr, ext, vm, I.p, true, false);
+  fill_header(hdr + static_cast<int64_t>(i) * kBHdr, ext, vm, I.p, true, I.rel != 0);
+}
+
+// ---- nearest squared distance of every query of the relative-weight instances ----
+__global__ __launch_bounds__(kWG) void kb_rmin_init(unsigned int* __restrict__ rmin, int64_t mtot) {
+  for (int64_t g = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; g < mtot;
+       g += static_cast<int64_t>(gridDim.x) * kWG)
+    rmin[g] = __builtin_bit_cast(unsigned int, __builtin_huge_valf());
+}
+
+// One workgroup per work item of a relative-weight instance: the item's data chunk goes
+// through LDS tiles, each lane keeps the smallest squared distance (scaled FP32 units, the
+// arithmetic of the sweep) of its queries and folds it into rmin.
+template <int DIM>
+__device__ __forceinline__ void kb_rmin_item(const BInst& I, const BItem& it, const double* __restrict__ hdr,
+                                             unsigned int* __restrict__ rmin, P4<float> (*tile)[kTile]) {
+  const int tid = threadIdx.x;
+  const int64_t q0 = static_cast<int64_t>(it.qblock) * (kWG * kBQ);
+  const int64_t jb = static_cast<int64_t>(it.chunk) * I.chunk;
+  const int64_t je = (jb + I.chunk < I.n) ? jb + I.chunk : I.n;
+  const float s = static_cast<float>(hdr[H_SCALE]);
+  float qc[kBQ][3], mn[kBQ];
+  int64_t qi[kBQ];
+#pragma unroll
+  for (int k = 0; k < kBQ; ++k) {
+    qi[k] = q0 + tid + static_cast<int64_t>(k) * kWG;
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (qi[k] < I.m) r = I.query[qi[k]];
+    qc[k][0] = r.x * s;
+    qc[k][1] = r.y * s;
+    qc[k][2] = r.z * s;
+    mn[k] = __builtin_huge_valf();
+  }
+  const int ntiles = static_cast<int>((je - jb + kTile - 1) / kTile);
+  for (int t = 0; t < ntiles; ++t) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t j = jb + static_cast<int64_t>(t) * kTile + u * kWG + tid;
+      P4<float> r;
+      if (j < je) {
+        const float4 d = I.data[j];
+        r.x = d.x * s;
+        r.y = d.y * s;
+        r.z = d.z * s;
+      } else {  // padding record: infinitely far
+        r.x = r.y = r.z = __builtin_huge_valf();
+      }
+      r.w = 0.f;
+      tile[0][u * kWG + tid] = r;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int jj = 0; jj < kTile; ++jj) {
+      const P4<float> d = tile[0][jj];
+#pragma unroll
+      for (int k = 0; k < kBQ; ++k) {
+        const float r2 = sqdist<float, DIM>(qc[k], d);
+        mn[k] = r2 < mn[k] ? r2 : mn[k];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kBQ; ++k)
+    if (qi[k] < I.m) atomicMin(&rmin[I.q_off + qi[k]], __builtin_bit_cast(unsigned int, mn[k]));
+}
+
+__global__ __launch_bounds__(kWG) void kb_rmin(const BInst* __restrict__ inst, const BItem* __restrict__ items,
+                                               int nitems, const double* __restrict__ hdr,
+                                               unsigned int* __restrict__ rmin) {
+  __shared__ P4<float> tile[2][kTile];
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {  // uniform over the workgroup
+    const BItem it = items[w];
+    const BInst I = inst[it.inst];
+    const double* h = hdr + static_cast<int64_t>(it.inst) * kBHdr;
+    if (I.dim == 3)
+      kb_rmin_item<3>(I, it, h, rmin, tile);
+    else
+      kb_rmin_item<2>(I, it, h, rmin, tile);
+  }
 }
 
 // ---- persistent sweep ----
-template <int DIM, int PM>
+template <int DIM, int PM, bool REL = false>
 __device__ __forceinline__ void kb_item(const BInst& I, const BItem& it, const double* __restrict__ hdr,
-                                        double2* __restrict__ part, P4<float> (*tile)[kTile]) {
+                                        double2* __restrict__ part, P4<float> (*tile)[kTile],
+                                        const unsigned int* __restrict__ rmin) {
   const int tid = threadIdx.x;
   const int64_t q0 = static_cast<int64_t>(it.qblock) * (kWG * kBQ);
   const int64_t jb = static_cast<int64_t>(it.chunk) * I.chunk;
@@ -167,23 +251,30 @@ __device__ __forceinline__ void kb_item(const BInst& I, const BItem& it, const d
     }
   };
   const int ntiles = static_cast<int>((je - jb + kTile - 1) / kTile);
-  float one[kBQ];  // direct weights: no per-query scaling
+  float sg[kBQ];  // per-query scale of the relative weights (1: direct weights)
+  double fs[kBQ];
 #pragma unroll
-  for (int k = 0; k < kBQ; ++k) one[k] = 1.f;
+  for (int k = 0; k < kBQ; ++k) {
+    sg[k] = 1.f;
+    fs[k] = 1.0;
+    if constexpr (REL) {
+      if (qi[k] < I.m) rel_from_min(__builtin_bit_cast(float, rmin[I.q_off + qi[k]]), I.p, sg[k], fs[k]);
+    }
+  }
   fetch(0);
   put(0);
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) fetch(t + 1);
-    fwd_tile<float, DIM, PM, kBQ, false, 4>(tile[t & 1], 0, qc, qi, I.nhp, one, nh, nl, dh, dl);
+    fwd_tile<float, DIM, PM, kBQ, false, 4, false, REL>(tile[t & 1], 0, qc, qi, I.nhp, sg, nh, nl, dh, dl);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < kBQ; ++k) {
     if (qi[k] < I.m) {
-      const double num = static_cast<double>(nh[k]) + static_cast<double>(nl[k]);
-      const double den = static_cast<double>(dh[k]) + static_cast<double>(dl[k]);
+      const double num = (static_cast<double>(nh[k]) + static_cast<double>(nl[k])) * fs[k];
+      const double den = (static_cast<double>(dh[k]) + static_cast<double>(dl[k])) * fs[k];
       part[I.part_off + static_cast<int64_t>(it.chunk) * I.m + qi[k]] = make_double2(num, den);
     }
   }
@@ -192,7 +283,8 @@ __device__ __forceinline__ void kb_item(const BInst& I, const BItem& it, const d
 __global__ __launch_bounds__(kWG) void kb_sweep(const BInst* __restrict__ inst, const BItem* __restrict__ items,
                                                 int nitems, int* __restrict__ counter,
                                                 const double* __restrict__ hdr,
-                                                double2* __restrict__ part) {
+                                                double2* __restrict__ part,
+                                                const unsigned int* __restrict__ rmin) {
   __shared__ P4<float> tile[2][kTile];
   __shared__ int claim;
   for (;;) {
@@ -204,23 +296,28 @@ __global__ __launch_bounds__(kWG) void kb_sweep(const BInst* __restrict__ inst, 
     const BItem it = items[w];
     const BInst I = inst[it.inst];
     const double* h = hdr + static_cast<int64_t>(it.inst) * kBHdr;
-    if (I.dim == 3) {
+    if (I.rel) {
+      if (I.dim == 3)
+        kb_item<3, PM_GEN, true>(I, it, h, part, tile, rmin);
+      else
+        kb_item<2, PM_GEN, true>(I, it, h, part, tile, rmin);
+    } else if (I.dim == 3) {
       switch (I.pmode) {
-        case PM_1: kb_item<3, PM_1>(I, it, h, part, tile); break;
-        case PM_2: kb_item<3, PM_2>(I, it, h, part, tile); break;
-        case PM_3: kb_item<3, PM_3>(I, it, h, part, tile); break;
-        case PM_4: kb_item<3, PM_4>(I, it, h, part, tile); break;
-        case PM_25: kb_item<3, PM_25>(I, it, h, part, tile); break;
-        default: kb_item<3, PM_GEN>(I, it, h, part, tile); break;
+        case PM_1: kb_item<3, PM_1>(I, it, h, part, tile, rmin); break;
+        case PM_2: kb_item<3, PM_2>(I, it, h, part, tile, rmin); break;
+        case PM_3: kb_item<3, PM_3>(I, it, h, part, tile, rmin); break;
+        case PM_4: kb_item<3, PM_4>(I, it, h, part, tile, rmin); break;
+        case PM_25: kb_item<3, PM_25>(I, it, h, part, tile, rmin); break;
+        default: kb_item<3, PM_GEN>(I, it, h, part, tile, rmin); break;
       }
     } else {
       switch (I.pmode) {
-        case PM_1: kb_item<2, PM_1>(I, it, h, part, tile); break;
-        case PM_2: kb_item<2, PM_2>(I, it, h, part, tile); break;
-        case PM_3: kb_item<2, PM_3>(I, it, h, part, tile); break;
-        case PM_4: kb_item<2, PM_4>(I, it, h, part, tile); break;
-        case PM_25: kb_item<2, PM_25>(I, it, h, part, tile); break;
-        default: kb_item<2, PM_GEN>(I, it, h, part, tile); break;
+        case PM_1: kb_item<2, PM_1>(I, it, h, part, tile, rmin); break;
+        case PM_2: kb_item<2, PM_2>(I, it, h, part, tile, rmin); break;
+        case PM_3: kb_item<2, PM_3>(I, it, h, part, tile, rmin); break;
+        case PM_4: kb_item<2, PM_4>(I, it, h, part, tile, rmin); break;
+        case PM_25: kb_item<2, PM_25>(I, it, h, part, tile, rmin); break;
+        default: kb_item<2, PM_GEN>(I, it, h, part, tile, rmin); break;
       }
     }
   }
@@ -386,12 +483,15 @@ struct idw_plan {
   int64_t part_elems = 0;  // double2 partial slots
   int grid = 0;            // persistent workgroups
   int chunk_target = 0;
+  int nrel_items = 0;      // work items of the relative-weight instances (nearest pass)
   std::vector<BInst> host_inst;
   BInst* d_inst = nullptr;
   BItem* d_items = nullptr;
+  BItem* d_rel_items = nullptr;
   size_t ws_bytes = 0;
   // workspace sections
   size_t o_hdr = 0, o_bbox = 0, o_counter = 0, o_part = 0, o_flag = 0, o_bcnt = 0, o_list = 0, o_count = 0;
+  size_t o_rmin = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -440,6 +540,7 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
     b.dim = s.data.dim;
     const int pm = pmode_of(s.p);
     b.pmode = pm;
+    b.rel = s.p >= kRelP ? 1 : 0;
     b.p = s.p;
     b.nhp = static_cast<float>(-0.5 * s.p);
     b.q_off = qoff;
@@ -461,10 +562,14 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
   std::stable_sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.cost > b.cost; });
   std::vector<BItem> items(cands.size());
   for (size_t k = 0; k < cands.size(); ++k) items[k] = cands[k].it;
+  std::vector<BItem> rel_items;
+  for (const BItem& it : items)
+    if (hi[it.inst].rel) rel_items.push_back(it);
 
   idw_plan* P = new idw_plan();
   P->count = count;
   P->nitems = static_cast<int>(items.size());
+  P->nrel_items = static_cast<int>(rel_items.size());
   P->mtot = qoff;
   P->part_elems = poff;
   P->chunk_target = chunk_target;
@@ -480,13 +585,16 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
   P->grid = grid_req > 0 ? grid_req : cus * 2;
   if (P->grid > P->nitems && P->nitems > 0) P->grid = P->nitems;
   if (hipMalloc(&P->d_inst, sizeof(BInst) * count) != hipSuccess ||
-      hipMalloc(&P->d_items, sizeof(BItem) * std::max<size_t>(1, items.size())) != hipSuccess) {
+      hipMalloc(&P->d_items, sizeof(BItem) * std::max<size_t>(1, items.size())) != hipSuccess ||
+      hipMalloc(&P->d_rel_items, sizeof(BItem) * std::max<size_t>(1, rel_items.size())) != hipSuccess) {
     idw_batched_plan_destroy(P);
     return fail(IDW_ENOMEM, "plan allocation failed");
   }
   if (hipMemcpy(P->d_inst, hi.data(), sizeof(BInst) * count, hipMemcpyHostToDevice) != hipSuccess ||
       (!items.empty() &&
-       hipMemcpy(P->d_items, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess)) {
+       hipMemcpy(P->d_items, items.data(), sizeof(BItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess) ||
+      (!rel_items.empty() && hipMemcpy(P->d_rel_items, rel_items.data(), sizeof(BItem) * rel_items.size(),
+                                       hipMemcpyHostToDevice) != hipSuccess)) {
     idw_batched_plan_destroy(P);
     return fail(IDW_EDEVICE, "plan upload failed");
   }
@@ -507,6 +615,7 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
   P->o_flag = take(static_cast<size_t>(mt));
   P->o_bcnt = take(sizeof(int) * static_cast<size_t>(nb + 1));
   P->o_list = take(sizeof(int) * static_cast<size_t>(mt));
+  P->o_rmin = take(P->nrel_items > 0 ? sizeof(unsigned int) * static_cast<size_t>(mt) : 0);
   P->ws_bytes = off;
   if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     idw_batched_plan_destroy(P);
@@ -533,12 +642,21 @@ static hipError_t enqueue_batched(idw_plan* P, char* ws, hipStream_t st) {
   uint8_t* flag = reinterpret_cast<uint8_t*>(ws + P->o_flag);
   int* bcnt = reinterpret_cast<int*>(ws + P->o_bcnt);
   int* list = reinterpret_cast<int*>(ws + P->o_list);
+  unsigned int* rmin = P->nrel_items > 0 ? reinterpret_cast<unsigned int*>(ws + P->o_rmin) : nullptr;
   hipLaunchKernelGGL(kb_reset, dim3(1), dim3(64), 0, st, counter);
   hipLaunchKernelGGL(kb_bbox, dim3(kBboxBlocks, P->count), dim3(kWG), 0, st, di, bbox);
   hipLaunchKernelGGL(kb_bbox_final, dim3((P->count + 63) / 64), dim3(64), 0, st, di, P->count, kBboxBlocks,
                      bbox, hdr);
+  if (P->nrel_items > 0) {  // nearest squared distance of the relative-weight instances' queries
+    const int64_t ib = (P->mtot + kWG - 1) / kWG;
+    hipLaunchKernelGGL(kb_rmin_init, dim3(static_cast<unsigned>(ib < 4096 ? ib : 4096)), dim3(kWG), 0, st, rmin,
+                       P->mtot);
+    hipLaunchKernelGGL(kb_rmin, dim3(static_cast<unsigned>(std::min(P->nrel_items, 2048))), dim3(kWG), 0, st, di,
+                       P->d_rel_items, P->nrel_items, hdr, rmin);
+  }
   if (P->nitems > 0)
-    hipLaunchKernelGGL(kb_sweep, dim3(P->grid), dim3(kWG), 0, st, di, P->d_items, P->nitems, counter, hdr, part);
+    hipLaunchKernelGGL(kb_sweep, dim3(P->grid), dim3(kWG), 0, st, di, P->d_items, P->nitems, counter, hdr, part,
+                       rmin);
   if (P->mtot > 0) {
     hipLaunchKernelGGL(kb_merge, dim3(static_cast<unsigned>((P->mtot + kWG - 1) / kWG)), dim3(kWG), 0, st, di,
                        P->count, P->mtot, hdr, part, flag);
@@ -593,6 +711,7 @@ void idw_batched_plan_destroy(idw_plan* plan) {
   if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
   if (plan->d_inst) (void)hipFree(plan->d_inst);
   if (plan->d_items) (void)hipFree(plan->d_items);
+  if (plan->d_rel_items) (void)hipFree(plan->d_rel_items);
   delete plan;
 }
 

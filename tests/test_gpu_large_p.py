@@ -272,3 +272,32 @@ def test_large_p_million_points_sampled():
     dqh = dq.cpu().numpy().astype(np.float64)[sel]
     e = np.max(np.abs(dqh - rb["dq"]), axis=1) / np.maximum(rb["dq_cond"], 1e-300)
     assert np.max(e) <= GTOL["f32"]
+
+
+@pytest.mark.parametrize("chunk", [1 << 30, 2048])
+def test_batched_large_p(chunk):
+    # A batch mixing direct (p = 2) and relative-weight (p = 8, 24) instances in 2-D and
+    # 3-D, with exact hits and near-coincident queries.  Unsplit (one chunk per instance)
+    # every instance is bit-identical to idw_forward; split, it agrees with the oracle.
+    from paper_1402_4986_amd import batched, workloads
+    specs = [(3000, 700, 2, 2.0), (5000, 900, 2, 8.0), (2500, 1100, 3, 24.0), (4000, 600, 3, 8.0)]
+    cases, insts = [], []
+    for k, (n, m, dim, p) in enumerate(specs):
+        x, z, q = _case(1200 + k, n, m, dim, hits=3, near=2)
+        cases.append((x, z, q, dim, p))
+        insts.append(dict(data=torch.tensor(workloads.pack_data(x, z, "aoas", "f32")[0], device="cuda"),
+                          query=torch.tensor(workloads.pack_query(q, "aoas", "f32")[0], device="cuda"),
+                          dim=dim, p=p, out_z=torch.empty(m, dtype=torch.float32, device="cuda")))
+    plan = batched.BatchedPlan(insts, chunk=chunk, tuning={})
+    plan.run()
+    torch.cuda.synchronize()
+    for (x, z, q, dim, p), inst in zip(cases, insts):
+        print(f"case chunk={chunk} dim={dim} p={p}", flush=True)
+        got = inst["out_z"].cpu().numpy().astype(np.float64)
+        ref = oracle.forward(x, z, q, p)
+        assert np.max(scaled_err(got, ref)) <= TOL["f32"]
+        np.testing.assert_array_equal(got[:3], ref["Z"][:3].astype(np.float32))
+        if chunk == 1 << 30:
+            Zs, _, _ = _forward(x, z, q, p, "aoas", split=1)
+            np.testing.assert_array_equal(got, Zs)
+    plan.close()

@@ -30,9 +30,11 @@ def _records(n, seed):
     return rec
 
 
-def test_max_data_count_forward_and_adjoint():
+@pytest.mark.parametrize("p", [2.0, 8.0])
+def test_max_data_count_forward_and_adjoint(p):
+    # p = 8 runs the relative weights: the nearest-distance pass and the scaled sweeps.
     n, m = NMAX, 2048
-    print(f"n={n} m={m} FP32 aoas", flush=True)
+    print(f"n={n} m={m} FP32 aoas p={p}", flush=True)
     data = _records(n, 900)
     hits = [0, n // 2, n - 1]
     vals = [1.25, -0.5, 2.0]
@@ -44,7 +46,7 @@ def test_max_data_count_forward_and_adjoint():
         query[k, :2] = data[j, :2]
     d = api.Points([data], n, 2, "aoas")
     q = api.Points([query], m, 2, "aoas")
-    Z, D = api.forward(d, q, 2.0, "f32")
+    Z, D = api.forward(d, q, p, "f32")
     torch.cuda.synchronize()
     Zh = Z.cpu().numpy()
     np.testing.assert_array_equal(Zh[:3], np.array(vals, dtype=np.float32))
@@ -52,7 +54,7 @@ def test_max_data_count_forward_and_adjoint():
     assert np.max(np.abs(Zh[3:] - 0.7)) <= 1e-5
     print("forward ok; adjoint", flush=True)
     g = torch.rand(m, device="cuda", dtype=torch.float32)
-    dz, dp, dq = api.backward(d, q, 2.0, g, Z, D, "f32")
+    dz, dp, dq = api.backward(d, q, p, g, Z, D, "f32")
     torch.cuda.synchronize()
     assert torch.isfinite(dp)
     tot = float(dz.double().sum())

@@ -117,16 +117,23 @@ typedef struct idw_points {
  *                     sweeps separately instead of the fused sweep (same results within
  *                     the stated tolerances; for comparison).  These sweeps use the direct
  *                     weights at every p (see "Large p in FP32").
+ *   near_search       nearest-distance searches (the near-coincidence check of candidate
+ *                     queries, and the nearest distance every query needs for the relative
+ *                     weights of p >= 6): 0 = a uniform grid over the data points, built in
+ *                     the workspace, for 65,536 to 2^26 data points (queries in dense cells
+ *                     fall back to brute force), brute force otherwise; 1 = brute force over
+ *                     all pairs always (for comparison; the results are the same bit for bit)
  *   reserved          must be zero
- * Negative fields, non-zero reserved fields and separate_adjoint outside {0, 1} are
- * rejected with IDW_EINVAL. */
+ * Negative fields, non-zero reserved fields, and separate_adjoint or near_search outside
+ * {0, 1} are rejected with IDW_EINVAL. */
 typedef struct idw_config {
   int32_t queries_per_lane;
   int32_t split;
   int32_t batch_chunk;
   int32_t batch_workgroups;
   int32_t separate_adjoint;
-  int32_t reserved[3];
+  int32_t near_search;
+  int32_t reserved[2];
 } idw_config;
 
 /* Library version string (static storage). */

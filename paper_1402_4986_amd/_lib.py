@@ -32,7 +32,8 @@ class IdwPoints(ctypes.Structure):
 class IdwConfig(ctypes.Structure):
     _fields_ = [("queries_per_lane", ctypes.c_int32), ("split", ctypes.c_int32),
                 ("batch_chunk", ctypes.c_int32), ("batch_workgroups", ctypes.c_int32),
-                ("separate_adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("separate_adjoint", ctypes.c_int32), ("near_search", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class IdwInstance(ctypes.Structure):

@@ -66,12 +66,15 @@ class Points:
         return Points(ts, coords.shape[0], coords.shape[1], "hybrid")
 
 
-def _cfg(queries_per_lane: int = 0, split: int = 0) -> Optional[IdwConfig]:
-    if not queries_per_lane and not split:
+def _cfg(queries_per_lane: int = 0, split: int = 0, near_search: int = 0,
+         separate: bool = False) -> Optional[IdwConfig]:
+    if not queries_per_lane and not split and not near_search and not separate:
         return None
     c = IdwConfig()
     c.queries_per_lane = queries_per_lane
     c.split = split
+    c.near_search = near_search
+    c.separate_adjoint = 1 if separate else 0
     return c
 
 
@@ -106,8 +109,9 @@ def workspace(data: Points, query: Points, precision: str, cfg: Optional[IdwConf
 
 def forward(data: Points, query: Points, p: float, precision: str = "f32", exclude_self: bool = False,
             queries_per_lane: int = 0, split: int = 0, out_z: Optional[torch.Tensor] = None,
-            out_den: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
-    """Z[m] (precision dtype) and D[m] (float64) for the query set (Eq. 1)."""
+            out_den: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, near_search: int = 0):
+    """Z[m] (precision dtype) and D[m] (float64) for the query set (Eq. 1).  near_search=1
+    makes the nearest-distance searches brute force (idw_config.near_search)."""
     lib = _lib.load()
     dt = _TORCH_DTYPE[precision]
     m = int(query.n)
@@ -116,7 +120,7 @@ def forward(data: Points, query: Points, p: float, precision: str = "f32", exclu
         out_z = torch.empty(m, dtype=dt, device=dev)
     if out_den is None:
         out_den = torch.empty(m, dtype=torch.float64, device=dev)
-    cfg = _cfg(queries_per_lane, split)
+    cfg = _cfg(queries_per_lane, split, near_search)
     if ws is None:
         ws = workspace(data, query, precision, cfg, backward=False)
     dc, qc = data.c(), query.c()
@@ -129,12 +133,13 @@ def forward(data: Points, query: Points, p: float, precision: str = "f32", exclu
 def backward(data: Points, query: Points, p: float, grad_out: torch.Tensor, saved_z: torch.Tensor,
              saved_den: torch.Tensor, precision: str = "f32", need_dz: bool = True, need_dp: bool = True,
              need_dq: bool = True, exclude_self: bool = False, ws: Optional[torch.Tensor] = None,
-             separate: bool = False, need_dx: bool = False):
+             separate: bool = False, need_dx: bool = False, near_search: int = 0):
     """(dz[n] or None, dp (0-d float64 tensor) or None, dq[m, dim] or None), followed by
     dx[n, dim] when need_dx (the gradient with respect to the data coordinates).
 
     separate=True runs the query-direction and data-direction sweeps as two kernels
-    instead of the fused FP32 sweep (for comparison)."""
+    instead of the fused FP32 sweep (for comparison); near_search=1 makes the
+    nearest-distance searches brute force."""
     lib = _lib.load()
     dt = _TORCH_DTYPE[precision]
     dev = data.device
@@ -145,13 +150,10 @@ def backward(data: Points, query: Points, p: float, grad_out: torch.Tensor, save
     dx = torch.empty((n, dim), dtype=dt, device=dev) if need_dx else None
     flags = (_lib.EXCLUDE_SELF if exclude_self else 0) | (_lib.NEED_DZ if need_dz else 0) \
         | (_lib.NEED_DP if need_dp else 0) | (_lib.NEED_DQ if need_dq else 0) | (_lib.NEED_DX if need_dx else 0)
+    cfg = _cfg(near_search=near_search, separate=separate)
     if ws is None:
-        ws = workspace(data, query, precision, need_dx=need_dx)
+        ws = workspace(data, query, precision, cfg, need_dx=need_dx)
     dc, qc = data.c(), query.c()
-    cfg = None
-    if separate:
-        cfg = IdwConfig()
-        cfg.separate_adjoint = 1
     check(lib.idw_backward(ctypes.byref(dc), ctypes.byref(qc), float(p), _lib.PRECISION_CODES[precision], flags,
                            _ptr(grad_out.contiguous()), _ptr(saved_z), _ptr(saved_den), _ptr(dz), _ptr(dp),
                            _ptr(dq), _ptr(dx), _ptr(ws), ws.numel(), _stream_handle(dev),

@@ -127,12 +127,14 @@ static bool same_query_layout(int a, int b) {
 
 int validate_config(const idw_config* cfg) {
   if (!cfg) return IDW_OK;
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < 2; ++k)
     if (cfg->reserved[k] != 0) return fail(IDW_EINVAL, "idw_config.reserved[%d] must be zero", k);
   if (cfg->queries_per_lane < 0 || cfg->split < 0 || cfg->batch_chunk < 0 || cfg->batch_workgroups < 0)
     return fail(IDW_EINVAL, "idw_config fields must not be negative");
   if (cfg->separate_adjoint != 0 && cfg->separate_adjoint != 1)
     return fail(IDW_EINVAL, "idw_config.separate_adjoint must be 0 or 1");
+  if (cfg->near_search != 0 && cfg->near_search != 1)
+    return fail(IDW_EINVAL, "idw_config.near_search must be 0 or 1");
   return IDW_OK;
 }
 
@@ -227,6 +229,17 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   w.part_f = take(w.split_f > 1 ? sizeof(double2) * static_cast<size_t>(w.split_f) * m : 0);
   w.fpart = take(sizeof(double4) * kFixGrid);
   w.fix_cmax = static_cast<int>(std::min<int64_t>(kFixGrid, std::max<int64_t>(1, cdiv(n, 4096))));
+  // grid of the nearest-distance searches
+  w.grid_on = n >= kGridMinN && n <= kGridMaxN && m > 0 && !(cfg && cfg->near_search == 1);
+  if (w.grid_on) {
+    w.grid_ncell = std::min<int64_t>(kGridMaxCells, std::max<int64_t>(1, n / kGridPerCell));
+    const int64_t nb = cdiv(w.grid_ncell, kGridScanBlock);
+    w.grid_cnt = take(sizeof(int) * static_cast<size_t>(w.grid_ncell + 1));
+    w.grid_start = take(sizeof(int) * static_cast<size_t>(w.grid_ncell + 1));
+    w.grid_bsum = take(sizeof(int) * static_cast<size_t>(nb + 1));
+    w.grid_rec = take(4 * (f64 ? sizeof(double) : sizeof(float)) * static_cast<size_t>(n));
+    w.grid_blist = take(sizeof(int) * static_cast<size_t>(m));
+  }
   w.fwd_total = off;  // the forward uses only the sections above
   w.part_q = take(sizeof(double4) * static_cast<size_t>(std::max(w.split_q, w.fused_ranges)) * m);
   w.part_z = take(sizeof(double) * static_cast<size_t>(std::max(w.split_z, w.fused_groups)) * n);
@@ -254,11 +267,12 @@ struct LayoutFns {
   hipError_t (*bwd_fixup)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_fused)(const BwdArgs&, hipStream_t);
   hipError_t (*near_check)(const NearArgs&, hipStream_t);
+  hipError_t (*grid)(const GridArgs&, bool, hipStream_t);
 };
 
 #define IDW_FNS(NAME)                                                                   \
   {fwd_sweep_##NAME, fwd_fixup_##NAME, bbox_##NAME,      bwd_query_##NAME, bwd_data_##NAME, \
-   bwd_datax_##NAME, bwd_fixup_##NAME, bwd_fused_##NAME, near_check_##NAME}
+   bwd_datax_##NAME, bwd_fixup_##NAME, bwd_fused_##NAME, near_check_##NAME, grid_##NAME}
 static const LayoutFns kFns[5] = {IDW_FNS(soa), IDW_FNS(aos), IDW_FNS(aoas), IDW_FNS(hybrid), IDW_FNS(soaos)};
 #undef IDW_FNS
 
@@ -288,21 +302,72 @@ hipError_t enqueue_header(const idw_points* data, double p, bool f64, bool rel, 
                     reinterpret_cast<double*>(ws + w.hdr), st);
 }
 
-// Nearest squared distance of every query (FP32 bits, scaled units) into the near_min
-// section: the relative-weight forward sweep takes each query's sigma from it.
-static hipError_t nearest_all(const LayoutFns& F, const idw_points* data, const idw_points* query, bool excl,
-                              char* ws, const WsPlan& w, hipStream_t st) {
+static GridArgs grid_args(const idw_points* data, const idw_points* query, bool f64, bool excl, char* ws,
+                          const WsPlan& w) {
+  GridArgs g;
+  g.data = dev_pts(data);
+  g.n = data->n;
+  g.query = dev_pts(query);
+  g.m = query->n;
+  g.dim = data->dim;
+  g.f64 = f64;
+  g.excl = excl;
+  g.hdr = reinterpret_cast<const double*>(ws + w.hdr);
+  g.hint = reinterpret_cast<int*>(ws + w.hdr + 256);
+  g.cnt = reinterpret_cast<int*>(ws + w.grid_cnt);
+  g.start = reinterpret_cast<int*>(ws + w.grid_start);
+  g.bsum = reinterpret_cast<int*>(ws + w.grid_bsum);
+  g.ncell_max = w.grid_ncell;
+  g.rec = ws + w.grid_rec;
+  g.route = reinterpret_cast<uint8_t*>(ws + w.flag);
+  g.minb = reinterpret_cast<unsigned long long*>(ws + w.near_min);
+  g.blist = reinterpret_cast<int*>(ws + w.grid_blist);
+  return g;
+}
+
+// Builds the grid when its gate (set by grid_setup) is open: counts, scan, scatter.
+static hipError_t grid_build(const LayoutFns& F, const GridArgs& g, hipStream_t st) {
+  hipError_t e = fill_zero(g.cnt, sizeof(int) * static_cast<size_t>(g.ncell_max + 1), st);
+  if (e != hipSuccess) return e;
+  return F.grid(g, true, st);
+}
+
+static NearArgs near_args(const idw_points* data, const idw_points* query, bool f64, bool excl, char* ws,
+                          const WsPlan& w) {
   NearArgs na;
   na.data = dev_pts(data);
   na.n = data->n;
   na.query = dev_pts(query);
   na.m = query->n;
   na.dim = data->dim;
-  na.f64 = false;
+  na.f64 = f64;
   na.excl = excl;
-  na.all = true;
   na.hdr = reinterpret_cast<const double*>(ws + w.hdr);
+  na.route = reinterpret_cast<uint8_t*>(ws + w.flag);
   na.minb = reinterpret_cast<unsigned long long*>(ws + w.near_min);
+  return na;
+}
+
+// Nearest squared distance of every query (FP32 bits, scaled units) into the near_min
+// section: the relative-weight forward sweep takes each query's sigma from it.  With the
+// grid: a ring search per query, and the brute-force kernels for the queries it hands
+// back; without it: the brute-force kernels over all queries.
+static hipError_t nearest_all(const LayoutFns& F, const idw_points* data, const idw_points* query, bool excl,
+                              char* ws, const WsPlan& w, hipStream_t st) {
+  NearArgs na = near_args(data, query, false, excl, ws, w);
+  if (!w.grid_on) {
+    na.all = true;
+    return F.near_check(na, st);
+  }
+  GridArgs g = grid_args(data, query, false, excl, ws, w);
+  g.nearest = true;
+  g.hint += kGridNearestSlots;  // its own gate and counters: the candidate check comes later
+  hipError_t e = grid_setup(g, 1, true, st);
+  if (e == hipSuccess) e = grid_build(F, g, st);
+  if (e == hipSuccess) e = F.grid(g, false, st);
+  if (e != hipSuccess) return e;
+  na.list = g.blist;  // the queries the ring search handed back
+  na.count = g.hint + GI_FALLBACK;
   return F.near_check(na, st);
 }
 
@@ -318,19 +383,22 @@ static hipError_t settle_routes(const LayoutFns& F, const idw_points* data, cons
   const int64_t m = query->n;
   hipError_t e = compact_flags(route, m, bcnt, list, count, F_CANDIDATE, st);
   if (e != hipSuccess) return e;
-  NearArgs na;
-  na.data = dev_pts(data);
-  na.n = data->n;
-  na.query = dev_pts(query);
-  na.m = m;
-  na.dim = data->dim;
-  na.f64 = f64;
-  na.excl = excl;
+  NearArgs na = near_args(data, query, f64, excl, ws, w);
   na.list = list;
   na.count = count;
-  na.hdr = reinterpret_cast<const double*>(ws + w.hdr);
-  na.route = route;
-  na.minb = reinterpret_cast<unsigned long long*>(ws + w.near_min);
+  if (w.grid_on) {
+    // Many candidates: the grid's fixed-radius check, then the brute-force kernels for the
+    // candidates it hands back; few: the brute-force kernels for all of them.
+    GridArgs g = grid_args(data, query, f64, excl, ws, w);
+    g.list = list;
+    if ((e = grid_setup(g, 0, true, st)) != hipSuccess) return e;
+    na.count = g.hint + GI_BRUTE;
+    if ((e = F.near_check(na, st)) != hipSuccess) return e;
+    if ((e = grid_build(F, g, st)) != hipSuccess) return e;
+    if ((e = F.grid(g, false, st)) != hipSuccess) return e;
+    na.list = g.blist;
+    na.count = g.hint + GI_FALLBACK;
+  }
   if ((e = F.near_check(na, st)) != hipSuccess) return e;
   return compact_flags(route, m, bcnt, list, count, F_FP64, st);
 }

@@ -28,6 +28,10 @@ struct WsPlan {
   size_t part_x = 0;     // data-coordinate partials, after everything else
   size_t total_x = 0;    // bytes forward + backward need with the data-coordinate gradient
   int fix_cmax = 1;
+  // grid of the nearest-distance searches (forward prefix; unused when grid_on is false)
+  bool grid_on = false;
+  int64_t grid_ncell = 0;  // most cells
+  size_t grid_cnt = 0, grid_start = 0, grid_bsum = 0, grid_rec = 0, grid_blist = 0;
 };
 
 int fail(int code, const char* fmt, ...);

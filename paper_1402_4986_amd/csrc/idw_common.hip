@@ -13,8 +13,11 @@ __global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ p
                                                     int dim, double p, int f32s, int rel,
                                                     double* __restrict__ hdr) {
   __shared__ double red[kWG];
+  __shared__ double bmn[3], bext[3];
   const int t = threadIdx.x;
   double ext = 0.0;
+  if (t < 3) bmn[t] = bext[t] = 0.0;
+  __syncthreads();
   for (int d = 0; d < dim; ++d) {
     double mn = __builtin_huge_val(), mx = -__builtin_huge_val();
     for (int b = t; b < nb; b += kWG) {
@@ -35,6 +38,10 @@ __global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ p
       __syncthreads();
     }
     ext = fmax(ext, mx - mn);
+    if (t == 0) {
+      bmn[d] = mn;
+      bext[d] = mx - mn;
+    }
   }
   double vm = 0.0;
   for (int b = t; b < nb; b += kWG) vm = fmax(vm, part[b * kBboxStride + 6]);
@@ -44,7 +51,14 @@ __global__ __launch_bounds__(kWG) void k_bbox_final(const double* __restrict__ p
     if (t < s) red[t] = fmax(red[t], red[t + s]);
     __syncthreads();
   }
-  if (t == 0) fill_header(hdr, ext, red[0], p, f32s != 0, rel != 0);
+  if (t == 0) {
+    fill_header(hdr, ext, red[0], p, f32s != 0, rel != 0);
+    const double s = hdr[H_SCALE];
+    for (int k = 0; k < 3; ++k) {  // the box in scaled units, for the grid searches
+      hdr[H_BMIN + k] = bmn[k] * s;
+      hdr[H_BEXT + k] = bext[k] * s;
+    }
+  }
 }
 
 hipError_t bbox_final(const double* part, int nblocks, int dim, double p, bool f32_scaling,
@@ -199,6 +213,117 @@ __global__ __launch_bounds__(kWG) void k_dp_final(const double* __restrict__ wg_
   for (int b = t; b < cnt; b += kWG) two_sum_acc(h, l, slot_dp[b]);
   const double tot = block_sum(h, red) + block_sum(l, red);
   if (t == 0) *grad_p = tot;
+}
+
+// ---- grid of the nearest-distance searches: geometry and gates, scan of the counts ----
+// Geometry: square cells of side h = (largest box side) / (floor(ncell_max^(1/dim)) - 1),
+// at least 2.5 times the near-coincidence distance (so the box q +- r' of the candidate
+// check meets at most two cells per axis), hence at most ncell_max cells.
+__global__ void k_grid_setup(double* __restrict__ hdr, int* __restrict__ hint, int dim, int64_t ncell_max,
+                             int mode, int grid_on, int64_t mall) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const int64_t cand = mode == 1 ? mall : static_cast<int64_t>(hint[0]);
+  const bool use = grid_on != 0 && cand > 0 && (mode == 1 || cand >= kGridMinCand);
+  hint[GI_FALLBACK] = 0;
+  hint[GI_BRUTE] = use ? 0 : static_cast<int>(cand);
+  hint[GI_GRID] = use ? static_cast<int>(cand) : 0;
+  if (!use) return;
+  double emax = 0.0;
+  for (int k = 0; k < dim; ++k) emax = fmax(emax, hdr[H_BEXT + k]);
+  int base = static_cast<int>(floor(pow(static_cast<double>(ncell_max), 1.0 / dim))) - 1;
+  if (base < 1) base = 1;
+  auto cells = [&](int b) {  // (b + 1)^dim
+    int64_t c = 1;
+    for (int k = 0; k < dim; ++k) c *= b + 1;
+    return c;
+  };
+  while (base > 1 && cells(base) > ncell_max) --base;  // pow may round the root up
+  double h = fmax(emax / base, 2.5 * sqrt(hdr[H_NEAR_R2]));
+  if (!(h > 0.0) || !(h < __builtin_huge_val())) h = 1.0;
+  hdr[H_GRID_H] = h;
+  hdr[H_GRID_INVH] = 1.0 / h;
+  for (int k = 0; k < 3; ++k) {
+    int g = 1;
+    if (k < dim) {
+      const double c = floor(hdr[H_BEXT + k] / h) + 1.0;
+      g = c < static_cast<double>(base + 1) ? static_cast<int>(c) : base + 1;
+      if (g < 1) g = 1;
+    }
+    hdr[H_GRID_G + k] = static_cast<double>(g);
+  }
+}
+
+__device__ __forceinline__ int64_t grid_ncell(const double* __restrict__ hdr) {
+  return static_cast<int64_t>(hdr[H_GRID_G]) * static_cast<int64_t>(hdr[H_GRID_G + 1]) *
+         static_cast<int64_t>(hdr[H_GRID_G + 2]);
+}
+
+constexpr int kScanPer = kGridScanBlock / kWG;  // cells per thread in the count scan
+
+__global__ __launch_bounds__(kWG) void k_grid_blocksum(const int* __restrict__ cnt, const double* __restrict__ hdr,
+                                                       const int* __restrict__ hint, int* __restrict__ bsum) {
+  __shared__ double red[kWG];
+  if (hint[GI_GRID] <= 0) {
+    if (threadIdx.x == 0) bsum[blockIdx.x] = 0;
+    return;
+  }
+  const int64_t ncell = grid_ncell(hdr);
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kGridScanBlock + threadIdx.x * kScanPer;
+  long long c = 0;
+  for (int u = 0; u < kScanPer; ++u)
+    if (base + u < ncell) c += cnt[base + u];
+  const double tot = block_sum(static_cast<double>(c), red);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = static_cast<int>(tot);
+}
+
+// start[c] = exclusive prefix of the counts; the counts become scatter cursors (= start);
+// start[ncell] = the number of points.
+__global__ __launch_bounds__(kWG) void k_grid_offsets(int* __restrict__ cnt, const double* __restrict__ hdr,
+                                                      const int* __restrict__ hint, const int* __restrict__ boff,
+                                                      int* __restrict__ start) {
+  __shared__ int buf[kWG];
+  if (hint[GI_GRID] <= 0) return;
+  const int64_t ncell = grid_ncell(hdr);
+  const int t = threadIdx.x;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kGridScanBlock + t * kScanPer;
+  int loc[kScanPer];
+  int c = 0;
+  for (int u = 0; u < kScanPer; ++u) {
+    loc[u] = base + u < ncell ? cnt[base + u] : 0;
+    c += loc[u];
+  }
+  buf[t] = c;
+  __syncthreads();
+  for (int off = 1; off < kWG; off <<= 1) {  // Hillis-Steele inclusive scan
+    const int add = t >= off ? buf[t - off] : 0;
+    __syncthreads();
+    buf[t] += add;
+    __syncthreads();
+  }
+  int pos = boff[blockIdx.x] + buf[t] - c;
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t cell = base + u;
+    if (cell < ncell) {
+      start[cell] = pos;
+      cnt[cell] = pos;
+      pos += loc[u];
+      if (cell == ncell - 1) start[ncell] = pos;
+    }
+  }
+}
+
+hipError_t grid_setup(const GridArgs& a, int mode, bool grid_on, hipStream_t st) {
+  hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, st, const_cast<double*>(a.hdr), a.hint, a.dim,
+                     a.ncell_max, mode, grid_on ? 1 : 0, a.m);
+  return hipGetLastError();
+}
+
+hipError_t grid_scan(const GridArgs& a, hipStream_t st) {
+  const int nb = static_cast<int>((a.ncell_max + kGridScanBlock - 1) / kGridScanBlock);
+  hipLaunchKernelGGL(k_grid_blocksum, dim3(nb), dim3(kWG), 0, st, a.cnt, a.hdr, a.hint, a.bsum);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kWG), 0, st, a.bsum, nb, a.hint + GI_TOTAL);
+  hipLaunchKernelGGL(k_grid_offsets, dim3(nb), dim3(kWG), 0, st, a.cnt, a.hdr, a.hint, a.bsum, a.start);
+  return hipGetLastError();
 }
 
 hipError_t bwd_qmerge(const BwdArgs& a, bool f64, hipStream_t st) {

@@ -277,8 +277,35 @@ enum HdrSlot {
   H_GEO_U = 9,     // near-coincidence threshold, caller units
   H_NEAR_R2 = 10,  // squared near-coincidence distance (1e-6 extent s)^2, scaled units
   H_REL = 11,      // 1 when the FP32 sweeps use per-query relative weights (large p), else 0
-  H_COUNT_I = 32   // int slots start at byte 256: [0] flagged count
+  H_BMIN = 12,     // [12..14] lower corner of the data bounding box, scaled units
+  H_BEXT = 15,     // [15..17] sides of the data bounding box, scaled units
+  H_GRID_H = 18,   // side of a grid cell (nearest-distance searches), scaled units
+  H_GRID_INVH = 19,
+  H_GRID_G = 20,   // [20..22] cells along each axis (1 along unused axes)
+  H_COUNT_I = 32   // int slots start at byte 256: [0] flagged count, then GridInt
 };
+
+// Int slots of the header after the flagged count, used by the grid searches: the
+// candidate check at [1..4], the ring search of every query at [5..8] (the same layout
+// shifted by kGridNearestSlots).
+enum GridInt {
+  GI_FALLBACK = 1,  // queries the grid handed to the brute-force check (appended to a list)
+  GI_BRUTE = 2,     // queries the brute-force check takes directly (few candidates)
+  GI_GRID = 3,      // queries the grid search takes (0: the grid is not built this call)
+  GI_TOTAL = 4      // scan total of the cell counts (the number of data points)
+};
+constexpr int kGridNearestSlots = 4;
+
+// Grid of the nearest-distance searches: used for n in [kGridMinN, kGridMaxN] (below, the
+// brute-force check is as cheap; above, the records would take too much workspace), about
+// kGridPerCell points per cell, at most kGridMaxCells cells; the candidate check builds it
+// only for at least kGridMinCand candidates (a build costs about one pass over the data).
+constexpr int64_t kGridMinN = 65536;
+constexpr int64_t kGridMaxN = int64_t(1) << 26;
+constexpr int64_t kGridPerCell = 4;
+constexpr int64_t kGridMaxCells = int64_t(1) << 22;
+constexpr int kGridMinCand = 4096;
+constexpr int kGridScanBlock = 4096;  // cells per block of the count scan (16 per thread)
 
 // From this exponent on the FP32 sweeps use relative weights: a query's weights are taken
 // relative to a power of two near its largest one, w' = (r2 sigma)^(-p/2) = w sigma^(-p/2)

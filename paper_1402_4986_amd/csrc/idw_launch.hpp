@@ -95,6 +95,29 @@ struct NearArgs {
   bool all = false;  // every query 0..m-1 (list and count unused); no route is written
 };
 
+// The grid of the nearest-distance searches (idw_grid.hpp).
+struct GridArgs {
+  DevPts data;
+  int64_t n = 0;
+  DevPts query;
+  int64_t m = 0;
+  int dim = 2;
+  bool f64 = false;
+  bool excl = false;
+  bool nearest = false;              // search: ring search over all queries, else candidate check
+  const double* hdr = nullptr;
+  int* hint = nullptr;               // header int slots (flagged count, then GridInt)
+  int* cnt = nullptr;                // [ncell_max + 1] cell counts, then scatter cursors
+  int* start = nullptr;              // [ncell_max + 1] first record of each cell
+  int* bsum = nullptr;               // [scan blocks] block sums of the counts
+  int64_t ncell_max = 0;
+  void* rec = nullptr;               // [n] P4<T>: scaled coordinates and point index
+  const int* list = nullptr;         // candidate check: candidate queries
+  uint8_t* route = nullptr;          // candidate check: QueryRoute written per candidate
+  unsigned long long* minb = nullptr;  // ring search: nearest squared distance (bits)
+  int* blist = nullptr;              // [m] queries handed to the brute-force check
+};
+
 constexpr int kTile = 512;        // data points staged in LDS per tile (2 per thread)
 constexpr int kFixGrid = 1024;    // workgroups of the FP64 fix-up kernels
 constexpr int kCountBlock = 4096; // flags per compaction block (16 per thread)
@@ -110,7 +133,8 @@ constexpr int kCountBlock = 4096; // flags per compaction block (16 per thread)
   hipError_t bwd_datax_##NAME(const BwdArgs& a, bool f64, hipStream_t st);       \
   hipError_t bwd_fixup_##NAME(const BwdArgs& a, bool f64, hipStream_t st);      \
   hipError_t bwd_fused_##NAME(const BwdArgs& a, hipStream_t st);                 \
-  hipError_t near_check_##NAME(const NearArgs& a, hipStream_t st);
+  hipError_t near_check_##NAME(const NearArgs& a, hipStream_t st);              \
+  hipError_t grid_##NAME(const GridArgs& a, bool build, hipStream_t st);
 
 IDW_DECLARE_LAYOUT(soa)
 IDW_DECLARE_LAYOUT(aos)
@@ -132,5 +156,9 @@ hipError_t bwd_zmerge(const BwdArgs& a, bool f64, hipStream_t st);
 hipError_t bwd_xmerge(const BwdArgs& a, int split, bool f64, hipStream_t st);
 hipError_t dp_final(const double* wg_dp, int nwg, const double* slot_dp, const int* count,
                     double* grad_p, hipStream_t st);
+// Grid geometry and the per-call gates (mode 0: candidate check of hint[0] candidates; mode
+// 1: ring search of all m queries), then the exclusive scan of the cell counts.
+hipError_t grid_setup(const GridArgs& a, int mode, bool grid_on, hipStream_t st);
+hipError_t grid_scan(const GridArgs& a, hipStream_t st);
 
 }  // namespace idw

@@ -4,6 +4,7 @@
 #include "idw_bwd.hpp"
 #include "idw_bwd_fused.hpp"
 #include "idw_fwd.hpp"
+#include "idw_grid.hpp"
 #include "idw_launch.hpp"
 
 #if !defined(IDW_LAYOUT) || !defined(IDW_LAYOUT_NAME)
@@ -63,6 +64,10 @@ hipError_t IDW_CAT(bwd_fixup_, IDW_LAYOUT_NAME)(const BwdArgs& a, bool f64, hipS
 
 hipError_t IDW_CAT(near_check_, IDW_LAYOUT_NAME)(const NearArgs& a, hipStream_t st) {
   return launch_near_check<IDW_LAYOUT>(a, st);
+}
+
+hipError_t IDW_CAT(grid_, IDW_LAYOUT_NAME)(const GridArgs& a, bool build, hipStream_t st) {
+  return launch_grid<IDW_LAYOUT>(a, build, st);
 }
 
 hipError_t IDW_CAT(bwd_fused_, IDW_LAYOUT_NAME)(const BwdArgs& a, hipStream_t st) {

@@ -214,7 +214,8 @@ def test_kahan_precision_is_fp32_storage_with_its_own_limits(lib):
 
 
 @pytest.mark.parametrize("field,value", [("reserved", 1), ("split", -1), ("queries_per_lane", -4),
-                                         ("batch_chunk", -1), ("separate_adjoint", 2)])
+                                         ("batch_chunk", -1), ("separate_adjoint", 2), ("near_search", 2),
+                                         ("near_search", -1)])
 def test_config_fields_are_validated(lib, field, value):
     d = _pts(1000, 2, _lib.AOAS)
     q = _pts(500, 2, _lib.AOAS, base=0x20000000)

@@ -271,10 +271,11 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         out["forward_ms_f32_kahan"] = round(e0.elapsed_time(e1) / 2, 3)
-        # large exponents (relative weights from p = 6 on): forward and the full adjoint of
-        # the same records at p = 8 and 32 (one untimed call each, then the mean of two)
-        lp = {}
-        for pl in (8.0, 32.0):
+        # other exponents, forward and the full adjoint of the same records (one untimed call
+        # each, then the mean of two): p = 0.5 and 1 (nearly every query is a near-coincidence
+        # candidate, settled through the grid) and p = 8 and 32 (relative weights)
+        sp, lp = {}, {}
+        for pl in (0.5, 1.0, 8.0, 32.0):
             api.forward(data, query, pl, "f32", out_z=Z, out_den=D, ws=ws)
             api.backward(data, query, pl, gt, Z, D, "f32", ws=ws)
             torch.cuda.synchronize()
@@ -287,8 +288,9 @@ def main():
                 api.backward(data, query, pl, gt, Z, D, "f32", ws=ws)
             e[2].record()
             torch.cuda.synchronize()
-            lp[str(pl)] = {"forward": round(e[0].elapsed_time(e[1]) / 2, 3),
-                           "adjoint": round(e[1].elapsed_time(e[2]) / 2, 3)}
+            (lp if pl >= 6.0 else sp)[str(pl)] = {"forward": round(e[0].elapsed_time(e[1]) / 2, 3),
+                                                  "adjoint": round(e[1].elapsed_time(e[2]) / 2, 3)}
+        out["small_p_ms"] = sp
         out["large_p_ms"] = lp
         api.forward(data, query, p, "f32", out_z=Z, out_den=D, ws=ws)
         torch.cuda.synchronize()

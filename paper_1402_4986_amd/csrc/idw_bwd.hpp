@@ -70,17 +70,17 @@ __device__ __forceinline__ void wterms(double r2, double nhp, double& w, double&
   if constexpr (NDP || PM == PM_GEN) lg = log2_64(r2);
   if constexpr (PM == PM_GEN) {
     w = exp2(nhp * lg);
-    if constexpr (NDQ) f = rcp64(r2);
+    if constexpr (NDQ) f = rcp64_w(r2);
   } else if constexpr (PM == PM_2) {
-    w = rcp64(r2);
+    w = rcp64_w(r2);
     if constexpr (NDQ) f = w;
   } else if constexpr (PM == PM_4) {
-    const double t = rcp64(r2);
+    const double t = rcp64_w(r2);
     w = t * t;
     if constexpr (NDQ) f = t;
   } else {
-    w = weight<PM>(r2, nhp);
-    if constexpr (NDQ) f = rcp64(r2);
+    w = weight_sweep<PM>(r2, nhp);
+    if constexpr (NDQ) f = rcp64_w(r2);
   }
 }
 
@@ -308,7 +308,7 @@ __device__ __forceinline__ void bwdd_tile(const P4<T>* __restrict__ tl, int64_t 
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
         const T r2 = sqdist<T, DIM>(xc[k], d);
-        T w = weight<PM>(r2, nhp);
+        T w = weight_sweep<PM>(r2, nhp);
         if constexpr (DIAG) {
           if (it + c0 + ii == xj[k]) w = T(0);
         }
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int64_t i = ib + static_cast<int64_t>(t) * kTile + u * kWG + tid;
-      rc[u][0] = rc[u][1] = rc[u][2] = infT<T>();
+      rc[u][0] = rc[u][1] = rc[u][2] = padT<T>();
       ra[u] = T(0);
       if (i < ie) {
         const double D = saved_den[i];

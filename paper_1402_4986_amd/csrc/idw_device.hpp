@@ -187,6 +187,63 @@ __device__ __forceinline__ double log2_64(double a) {
   return a == 0.0 ? -__builtin_huge_val() : a;
 }
 
+// The FP64 sweeps' weights need about 1e-14, not correct rounding (the FP64 tolerance is
+// 1e-12 of the condition scale): the hardware estimates (relative error below 6e-8 on
+// MI355X) refined by ONE Newton step, about 1e-14 relative (11 ulp measured for the
+// reciprocal).  No special-case handling: a = 0 or +inf gives NaN, so the sweeps pad with
+// far finite records (padT) and route exact hits, whose denominators turn NaN or
+// infinite, to the FP64 fix-up, which uses rcp64 / rsq64.
+__device__ __forceinline__ double rcp64_w(double a) {
+  const double y = __builtin_amdgcn_rcp(a);
+  return fma(y, fma(-a, y, 1.0), y);
+}
+__device__ __forceinline__ double rsq64_w(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  const double t = a * y;
+  return fma(0.5 * y, fma(-t, y, 1.0), y);
+}
+
+// Coordinate of padding records in the sweeps' LDS tiles: +inf in FP32 (every weight form
+// gives exactly 0 there), a far finite value in FP64 (weights of about 2^-800 and below,
+// which the one-step forms above handle).
+template <typename T>
+__device__ __forceinline__ T padT() {
+  return __builtin_huge_valf();
+}
+template <>
+__device__ __forceinline__ double padT<double>() {
+  return 0x1p400;
+}
+
+// Weight in the sweeps: weight<PM> in FP32; in FP64 the one-step forms for the fast classes.
+template <int PM>
+__device__ __forceinline__ float weight_sweep(float r2, float nhp) {
+  return weight<PM>(r2, nhp);
+}
+
+template <int PM>
+__device__ __forceinline__ double weight(double r2, double nhp);
+
+template <int PM>
+__device__ __forceinline__ double weight_sweep(double r2, double nhp) {
+  if constexpr (PM == PM_2) {
+    return rcp64_w(r2);
+  } else if constexpr (PM == PM_1) {
+    return rsq64_w(r2);
+  } else if constexpr (PM == PM_3) {
+    const double s = rsq64_w(r2);
+    return s * s * s;
+  } else if constexpr (PM == PM_4) {
+    const double t = rcp64_w(r2);
+    return t * t;
+  } else if constexpr (PM == PM_25) {
+    const double s = rsq64_w(r2);
+    return s * s * sqrt(s);
+  } else {
+    return weight<PM>(r2, nhp);
+  }
+}
+
 template <int PM>
 __device__ __forceinline__ double weight(double r2, double nhp) {
   if constexpr (PM == PM_2) {

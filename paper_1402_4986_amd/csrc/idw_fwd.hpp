@@ -91,7 +91,7 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
       for (int k = 0; k < Q; ++k) {
         T r2 = sqdist<T, DIM>(qc[k], d);
         if constexpr (REL) r2 *= sg[k];
-        T w = weight<PM>(r2, nhp);
+        T w = weight_sweep<PM>(r2, nhp);
         if constexpr (DIAG) {
           if (jt + jj == qi[k]) w = T(0);
         }
@@ -116,7 +116,7 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
       for (int k = 0; k < Q; ++k) {
         T r2 = sqdist<T, DIM>(qc[k], d);
         if constexpr (REL) r2 *= sg[k];
-        T w = weight<PM>(r2, nhp);
+        T w = weight_sweep<PM>(r2, nhp);
         if constexpr (DIAG) {
           if (jt + c0 + jj == qi[k]) w = T(0);
         }
@@ -205,8 +205,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
       const int64_t j = jb + static_cast<int64_t>(t) * kTile + u * kWG + tid;
       if (j < je) {
         Loader<T, DIM, L>::data(data, j, rc[u], rv[u]);
-      } else {  // padding record: infinitely far, zero value -> weight 0
-        rc[u][0] = rc[u][1] = rc[u][2] = infT<T>();
+      } else {  // padding record: far away, zero value -> weight (near) 0
+        rc[u][0] = rc[u][1] = rc[u][2] = padT<T>();
         rv[u] = T(0);
       }
     }

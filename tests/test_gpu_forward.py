@@ -113,6 +113,29 @@ def test_determinism_permutation_and_power_of_two_scaling():
     np.testing.assert_allclose(Ds, D1 / 1024.0, rtol=1e-15)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("p", [2.0, 8.0])
+def test_invariances_within_tolerance(prec, p):
+    # Eq. 1 is invariant under a permutation of the data points and commutes with an affine
+    # map of the values, Z(a z + b) = a Z + b.  The GPU results may differ by rounding only:
+    # the permuted run is held to the tolerance of the summation scale S; the mapped one to
+    # the tolerance of S_a + |a| S (S_a the mapped values' scale, which can be far smaller
+    # where a z + b crosses zero), plus the rounding of the mapped values themselves.
+    x, z, q = rand_case(14, 5000, 1500, 2, prec)
+    t = np.float32 if prec == "f32" else np.float64
+    ref = oracle.forward(x, z, q, p)
+    Z0, _ = gpu_forward(x, z, q, p, "aoas", prec)
+    perm = np.random.default_rng(15).permutation(len(x))
+    Zp, _ = gpu_forward(x[perm], z[perm], q, p, "aoas", prec)
+    assert np.max(np.abs(Zp - Z0) / ref["S"]) <= 2 * TOL[prec]
+    a, b = -2.5, 0.75
+    za = (a * z + b).astype(t).astype(np.float64)
+    Za, _ = gpu_forward(x, za, q, p, "aoas", prec)
+    refa = oracle.forward(x, za, q, p)
+    scale = refa["S"] + abs(a) * ref["S"]
+    assert np.max(np.abs(Za - (a * Z0 + b)) / scale) <= 2 * TOL[prec] + np.finfo(t).eps
+
+
 def test_large_coordinates_and_offsets():
     x, z, q = rand_case(13, 3000, 500, 2)
     Z, _ = gpu_forward(x * 1e5 + 3e5, z, q * 1e5 + 3e5, 2.0, "aoas", "f64")

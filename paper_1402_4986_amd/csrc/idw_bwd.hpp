@@ -67,9 +67,9 @@ __device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& f, 
 
 template <int PM, bool NDQ, bool NDP>
 __device__ __forceinline__ void wterms(double r2, double nhp, double& w, double& f, double& lg) {
-  if constexpr (NDP || PM == PM_GEN) lg = log2_64(r2);
+  if constexpr (NDP || PM == PM_GEN) lg = log2_t(r2);  // log2_table_init in the kernel
   if constexpr (PM == PM_GEN) {
-    w = exp2(nhp * lg);
+    w = exp2_t(nhp * lg);  // exp2_table_init in the kernel
     if constexpr (NDQ) f = rcp64_w(r2);
   } else if constexpr (PM == PM_2) {
     w = rcp64_w(r2);
@@ -207,6 +207,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 
   const int ntiles = static_cast<int>((je - jb + kTile - 1) / kTile);
   const bool excl = (flags & 1u) != 0;
+  if constexpr (sizeof(T) == 8 && (PM == PM_GEN || NDP)) log2_table_init();  // FP64 log2 (synchronised below)
+  if constexpr (sizeof(T) == 8 && PM == PM_GEN) exp2_table_init();
   fetch(0);
   put(0);
   __syncthreads();
@@ -386,6 +388,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 
   const int ntiles = static_cast<int>((ie - ib + kTile - 1) / kTile);
   const bool excl = (flags & 1u) != 0;
+  if constexpr (sizeof(T) == 8 && PM == PM_GEN) log2_table_init();  // FP64 log2 (synchronised below)
+  if constexpr (sizeof(T) == 8 && PM == PM_GEN) exp2_table_init();
   fetch(0);
   put(0);
   __syncthreads();
@@ -504,6 +508,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
   };
 
   const int ntiles = static_cast<int>((ie - ib + kTile - 1) / kTile);
+  if constexpr (sizeof(T) == 8 && PM == PM_GEN) log2_table_init();  // FP64 log2 (synchronised below)
+  if constexpr (sizeof(T) == 8 && PM == PM_GEN) exp2_table_init();
   fetch(0);
   put(0);
   __syncthreads();

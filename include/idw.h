@@ -113,10 +113,12 @@ typedef struct idw_points {
  *   batch_chunk       batched plans: data points per work item (rounded up to 512;
  *                     default 16384)
  *   batch_workgroups  batched plans: persistent workgroups (default 2 per compute unit)
- *   separate_adjoint  idw_backward, FP32: 1 = run the query-direction and data-direction
- *                     sweeps separately instead of the fused sweep (same results within
- *                     the stated tolerances; for comparison).  These sweeps use the direct
- *                     weights at every p (see "Large p in FP32").
+ *   separate_adjoint  idw_backward: 1 = run the query-direction and data-direction sweeps
+ *                     separately instead of the fused sweep (same results within the
+ *                     stated tolerances; for comparison).  These sweeps use the direct
+ *                     weights at every p (see "Large p in FP32").  The fused sweep serves
+ *                     FP32 requests with dz and dp/dq, with dx, or (p >= 6) any request,
+ *                     and FP64 requests with dz and dp/dq but no dx.
  *   near_search       nearest-distance searches (the near-coincidence check of candidate
  *                     queries, and the nearest distance every query needs for the relative
  *                     weights of p >= 6): 0 = a uniform grid over the data points, built in

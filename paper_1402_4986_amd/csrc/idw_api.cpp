@@ -200,16 +200,17 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   choose_split(n, cdiv(m, kWG * w.qq), 0, w.split_q, w.chunk_q);
   w.qz = f64 ? 2 : 4;
   choose_split(m > 0 ? m : 1, cdiv(n, kWG * w.qz), 0, w.split_z, w.chunk_z);
-  // fused FP32 adjoint: workgroup (group, range) sweeps data range `range` for the query
-  // blocks group, group + G, ...; about 1024 workgroups of 512 threads in all.  Ranges of
-  // 64K points balance the dz rows (groups x n doubles) against the query partials
-  // (ranges x m double4): about 1 GB at n = m = 1M.
-  if (!f64 && m > 0) {
+  // fused adjoint: workgroup (group, range) sweeps data range `range` for the query blocks
+  // group, group + G, ...; in FP32 about 1024 workgroups of 512 threads in all, in FP64
+  // about 2048 of 256.  Ranges of 64K points balance the dz rows (groups x n doubles)
+  // against the query partials (ranges x m double4): about 1 GB at n = m = 1M in FP32.
+  if (m > 0) {
     const int ranges = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, cdiv(n, 65536))));
     w.fused_chunk = cdiv(cdiv(n, ranges), kTile) * kTile;
     w.fused_ranges = static_cast<int>(cdiv(n, w.fused_chunk));
-    const int64_t nqb = cdiv(m, 512 * 2);
-    w.fused_groups = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nqb, cdiv(1024, w.fused_ranges))));
+    const int64_t nqb = cdiv(m, f64 ? 256 * 2 : 512 * 2);
+    const int64_t target = f64 ? 2048 : 1024;
+    w.fused_groups = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nqb, cdiv(target, w.fused_ranges))));
   }
   w.nbbox = static_cast<int>(std::min<int64_t>(1024, cdiv(n, kWG)));
   w.nwg_dp = static_cast<int>(cdiv(m, kWG));
@@ -265,7 +266,7 @@ struct LayoutFns {
   hipError_t (*bwd_data)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_datax)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*bwd_fixup)(const BwdArgs&, bool, hipStream_t);
-  hipError_t (*bwd_fused)(const BwdArgs&, hipStream_t);
+  hipError_t (*bwd_fused)(const BwdArgs&, bool, hipStream_t);
   hipError_t (*near_check)(const NearArgs&, hipStream_t);
   hipError_t (*grid)(const GridArgs&, bool, hipStream_t);
 };
@@ -662,14 +663,16 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
                       "near-coincidence check")))
     return rc;
   a.route = flag;
-  // The fused FP32 sweep pays off when both directions are needed: dz or dx with dp or dq,
-  // or dx alone (its per-pair factors are those of dq).
-  const bool fused = rel || (!f64 && (ndx || (ndz && (ndp || ndq))) && w.fused_groups > 0 && !separate);
-  if (fused) {  // one FP32 sweep for dp/dq and dz (and dx)
+  // The fused sweep pays off when both directions are needed: dz with dp or dq; in FP32
+  // also dx (alone or with the others: its per-pair factors are those of dq).  FP64 runs
+  // dx through the separate sweeps.
+  const bool both = ndz && (ndp || ndq);
+  const bool fused = rel || (w.fused_groups > 0 && !separate && (f64 ? (both && !ndx) : (ndx || both)));
+  if (fused) {  // one sweep for dp/dq and dz (and, in FP32, dx)
     a.fused_groups = w.fused_groups;
     a.fused_ranges = w.fused_ranges;
     a.fused_chunk = w.fused_chunk;
-    if ((rc = check_hip(timed(IDW_T_BWD_FUSED, st, [&] { return F.bwd_fused(a, st); }), "fused adjoint sweep")))
+    if ((rc = check_hip(timed(IDW_T_BWD_FUSED, st, [&] { return F.bwd_fused(a, f64, st); }), "fused adjoint sweep")))
       return rc;
     BwdArgs b = a;
     b.split_q = w.fused_ranges;

@@ -27,13 +27,30 @@
 
 namespace idw {
 
-constexpr int kBatch = 64;                   // data points per rotation batch (one wave)
-constexpr int kFTile = 512;                  // data points per LDS tile (8 batches)
-constexpr int kFBatches = kFTile / kBatch;
+constexpr int kBatch = 64;  // data points per rotation batch (one wave)
 
-// Lane L takes the running sum of lane L+1 (wave rotate left by one).
+// Data points per LDS tile: 512 in FP32 (8 batches), 256 in FP64 (the records are twice as
+// wide; with 256-thread workgroups the tiles, batches doubled, and the per-wave sums take
+// 40 KB of LDS).
+template <typename T>
+struct FusedShape {
+  static constexpr int TILE = sizeof(T) == 8 ? 256 : 512;
+  static constexpr int NT = sizeof(T) == 8 ? 256 : 512;  // threads per workgroup
+};
+constexpr int kFTile = FusedShape<float>::TILE;
+
+// Lane L takes the running sum of lane L+1 (wave rotate left by one); an FP64 value moves
+// as its two 32-bit halves.
 __device__ __forceinline__ float rotate_in(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double rotate_in(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned int>(b)), 0x134, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(static_cast<unsigned int>(b >> 32)), 0x134, 0xF, 0xF,
+                                             false);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned int>(hi)) << 32) |
+                                        static_cast<unsigned int>(lo));
 }
 
 // One 64-point batch.  MASK: some pairs must be skipped (padding records beyond the data
@@ -42,22 +59,20 @@ __device__ __forceinline__ float rotate_in(float v) {
 // REL: relative weights; the squared distance is multiplied by the query's sigma (sg)
 // before the weight terms, log2 r2 = log2(r2 sigma) - k (kq), and the X sums take the
 // coefficient a sigma (axq) so that they stay those of the direct form.
-template <int DIM, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool MASK, int UNR, bool REL = false>
-__device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, int lane, int64_t jb,
-                                            int64_t je, bool excl, const float (&qc)[Q][3],
-                                            const float (&zq)[Q], const float (&aq)[Q],
-                                            const float (&sg)[Q], const float (&kq)[Q],
-                                            const float (&axq)[Q], const int64_t (&qi)[Q], float nhp,
-                                            float (&ap)[Q], float (&ag)[Q][3], float (&ax)[3]) {
-  float acc = 0.f;
-  ax[0] = ax[1] = ax[2] = 0.f;
-  const P4<float>* r0 = rec + lane;
+template <typename T, int DIM, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool MASK, int UNR, bool REL = false>
+__device__ __forceinline__ T bwdf_batch(const P4<T>* __restrict__ rec, int lane, int64_t jb, int64_t je,
+                                        bool excl, const T (&qc)[Q][3], const T (&zq)[Q], const T (&aq)[Q],
+                                        const T (&sg)[Q], const T (&kq)[Q], const T (&axq)[Q],
+                                        const int64_t (&qi)[Q], T nhp, T (&ap)[Q], T (&ag)[Q][3], T (&ax)[3]) {
+  T acc = T(0);
+  ax[0] = ax[1] = ax[2] = T(0);
+  const P4<T>* r0 = rec + lane;
 #pragma unroll UNR
   for (int s = 0; s < kBatch; ++s) {
-    const P4<float> d = r0[s];
-    const float dv = (DIM == 3) ? d.w : d.z;
-    float sz = 0.f;
-    float sx[3] = {0.f, 0.f, 0.f};
+    const P4<T> d = r0[s];
+    const T dv = (DIM == 3) ? d.w : d.z;
+    T sz = T(0);
+    T sx[3] = {T(0), T(0), T(0)};
     int64_t j = 0;
     bool valid = true;
     if constexpr (MASK) {
@@ -66,47 +81,47 @@ __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, i
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      const float dx = qc[k][0] - d.x;
-      const float dy = qc[k][1] - d.y;
-      float dz = 0.f;
-      float r2 = dx * dx;
-      r2 = fmaf(dy, dy, r2);
+      const T dx = qc[k][0] - d.x;
+      const T dy = qc[k][1] - d.y;
+      T dz = T(0);
+      T r2 = dx * dx;
+      r2 = fmaT(dy, dy, r2);
       if constexpr (DIM == 3) {
         dz = qc[k][2] - d.z;
-        r2 = fmaf(dz, dz, r2);
+        r2 = fmaT(dz, dz, r2);
       }
-      float c = dv - zq[k];
-      float a = aq[k];
-      float av = REL ? axq[k] : a;
+      T c = dv - zq[k];
+      T a = aq[k];
+      T av = REL ? axq[k] : a;
       if constexpr (REL) r2 *= sg[k];
       if constexpr (MASK) {
         if (!valid || (excl && j == qi[k])) {
-          r2 = 1.f;
-          c = 0.f;
-          a = 0.f;
-          av = 0.f;
+          r2 = T(1);
+          c = T(0);
+          a = T(0);
+          av = T(0);
         }
       }
-      float w, f = 0.f, lg = 0.f;
+      T w, f = T(0), lg = T(0);
       wterms<PM, NDQ || NDX, NDP>(r2, nhp, w, f, lg);
       if constexpr (REL && NDP) lg -= kq[k];
-      const float t = w * c;
-      if constexpr (NDP) ap[k] = fmaf(t, lg, ap[k]);
+      const T t = w * c;
+      if constexpr (NDP) ap[k] = fmaT(t, lg, ap[k]);
       if constexpr (NDQ || NDX) {
-        const float u = t * f;  // (w / r2)(z - Z)
+        const T u = t * f;  // (w / r2)(z - Z)
         if constexpr (NDQ) {
-          ag[k][0] = fmaf(u, dx, ag[k][0]);
-          ag[k][1] = fmaf(u, dy, ag[k][1]);
-          if constexpr (DIM == 3) ag[k][2] = fmaf(u, dz, ag[k][2]);
+          ag[k][0] = fmaT(u, dx, ag[k][0]);
+          ag[k][1] = fmaT(u, dy, ag[k][1]);
+          if constexpr (DIM == 3) ag[k][2] = fmaT(u, dz, ag[k][2]);
         }
         if constexpr (NDX) {
-          const float v = av * u;
-          sx[0] = (k == 0) ? v * dx : fmaf(v, dx, sx[0]);
-          sx[1] = (k == 0) ? v * dy : fmaf(v, dy, sx[1]);
-          if constexpr (DIM == 3) sx[2] = (k == 0) ? v * dz : fmaf(v, dz, sx[2]);
+          const T v = av * u;
+          sx[0] = (k == 0) ? v * dx : fmaT(v, dx, sx[0]);
+          sx[1] = (k == 0) ? v * dy : fmaT(v, dy, sx[1]);
+          if constexpr (DIM == 3) sx[2] = (k == 0) ? v * dz : fmaT(v, dz, sx[2]);
         }
       }
-      sz = (k == 0) ? a * w : fmaf(a, w, sz);
+      sz = (k == 0) ? a * w : fmaT(a, w, sz);
     }
     acc = rotate_in(acc) + sz;
     if constexpr (NDX) {
@@ -120,47 +135,56 @@ __device__ __forceinline__ float bwdf_batch(const P4<float>* __restrict__ rec, i
 // Defaults measured on MI355X (1M queries x 256K data, 2-D, p = 2): 512-thread workgroups,
 // Q = 2, unroll 2, about 1024 workgroups in the grid: 13.6 VALU lane-slots per pair, against
 // 17.3 with 256-thread workgroups and 512 in the grid.
-constexpr int kFNT = 512;
+constexpr int kFNT = FusedShape<float>::NT;
 
 // Coordinate given to queries that are left out of a sweep (flagged for the FP64 fix-up):
 // far from every scaled data point, yet with r2 (< 3 * 2^120) and every product of the
 // pair terms finite, so that their zero factors a = 0 give exact zeros.
 constexpr float kFarF = 0x1p60f;
 
-template <int DIM, int L, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool REL = false, int UNR = 2, int WPE = 2,
-          int NT = kFNT>
+// T = float: the FP32 adjoint (with relative weights for large p, and the data-coordinate
+// sums); T = double: the FP64 adjoint of dz with dp and/or dq (the FP64 one-step and table
+// forms of the weights, no relative weights, no data-coordinate sums).
+template <typename T, int DIM, int L, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool REL = false, int UNR = 2,
+          int WPE = 2, int NT = FusedShape<T>::NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_fused(
-    DevPts data, int64_t n, DevPts query, int64_t m, int64_t chunk, int groups, float nhp, unsigned flags,
-    const double* __restrict__ hdr, const float* __restrict__ saved_z, const float* __restrict__ grad_out,
+    DevPts data, int64_t n, DevPts query, int64_t m, int64_t chunk, int groups, T nhp, unsigned flags,
+    const double* __restrict__ hdr, const T* __restrict__ saved_z, const T* __restrict__ grad_out,
     const double* __restrict__ saved_den, double4* __restrict__ part_q, double* __restrict__ part_z,
     double* __restrict__ part_x, const uint8_t* __restrict__ route, double pd) {
-  __shared__ P4<float> tile[2][2 * kFTile];   // batches stored twice in a row
-  constexpr int PPT = kFTile / NT;            // tile points staged per thread
-  __shared__ float zred[NT / 64][kFTile];    // per-wave dz sums of the current tile
-  __shared__ float xred[NDX ? NT / 64 : 1][NDX ? DIM * kFTile : 1];  // per-wave X sums
+  static_assert(sizeof(T) == 4 || (!REL && !NDX), "FP64: no relative weights, no data-coordinate sums");
+  constexpr int kFTile = FusedShape<T>::TILE;
+  constexpr int kFBatches = kFTile / kBatch;
+  __shared__ P4<T> tile[2][2 * kFTile];   // batches stored twice in a row
+  constexpr int PPT = kFTile / NT;        // tile points staged per thread
+  static_assert(PPT >= 1, "a tile holds at least one point per thread");
+  __shared__ T zred[NT / 64][kFTile];     // per-wave dz sums of the current tile
+  __shared__ T xred[NDX ? NT / 64 : 1][NDX ? DIM * kFTile : 1];  // per-wave X sums
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int qg = blockIdx.x;
   const int64_t jb = static_cast<int64_t>(blockIdx.y) * chunk;
   const int64_t je = (jb + chunk < n) ? jb + chunk : n;
-  const float s = static_cast<float>(hdr[H_SCALE]);
+  const T s = static_cast<T>(hdr[H_SCALE]);
   const double unit = hdr[H_DEN_UNIT];
   const bool excl = (flags & 1u) != 0;
+  if constexpr (sizeof(T) == 8 && (NDP || PM == PM_GEN)) log2_table_init();  // synchronised below
+  if constexpr (sizeof(T) == 8 && PM == PM_GEN) exp2_table_init();
   const int64_t qpb = static_cast<int64_t>(NT) * Q;
   const int64_t nqb = (m + qpb - 1) / qpb;
   const int ntiles = static_cast<int>((je - jb + kFTile - 1) / kFTile);
   double* zrow = part_z + static_cast<int64_t>(qg) * n;
   double* xrow = NDX ? part_x + static_cast<int64_t>(qg) * n * DIM : nullptr;
 
-  float rc[PPT][3], rv[PPT];
+  T rc[PPT][3], rv[PPT];
   auto fetch = [&](int t) {
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
       const int64_t j = jb + static_cast<int64_t>(t) * kFTile + u * NT + tid;
-      rc[u][0] = rc[u][1] = rc[u][2] = 0.f;
-      rv[u] = 0.f;
-      if (j < je) Loader<float, DIM, L>::data(data, j, rc[u], rv[u]);
+      rc[u][0] = rc[u][1] = rc[u][2] = T(0);
+      rv[u] = T(0);
+      if (j < je) Loader<T, DIM, L>::data(data, j, rc[u], rv[u]);
     }
   };
   auto put = [&](int b) {
@@ -168,7 +192,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
     for (int u = 0; u < PPT; ++u) {
       const int p = u * NT + tid;                        // point within the tile
       const int at = (p / kBatch) * (2 * kBatch) + (p % kBatch);
-      const P4<float> r = stage<float, DIM>(rc[u], rv[u], s);
+      const P4<T> r = stage<T, DIM>(rc[u], rv[u], s);
       tile[b][at] = r;
       tile[b][at + kBatch] = r;
     }
@@ -177,44 +201,47 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
   int first = 1;
   for (int64_t qb = qg; qb < nqb; qb += groups, first = 0) {
     const int64_t q0 = qb * qpb;
-    float qc[Q][3], zq[Q], aq[Q], sg[Q], kq[Q], axq[Q];
+    T qc[Q][3], zq[Q], aq[Q], sg[Q], kq[Q], axq[Q];
     int64_t qi[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       qi[k] = q0 + tid + static_cast<int64_t>(k) * NT;
-      float c[3] = {0.f, 0.f, 0.f};
+      T c[3] = {T(0), T(0), T(0)};
       bool ok = false;
-      zq[k] = 0.f;
-      aq[k] = 0.f;
-      sg[k] = 1.f;
-      kq[k] = 0.f;
-      axq[k] = 0.f;
+      zq[k] = T(0);
+      aq[k] = T(0);
+      sg[k] = T(1);
+      kq[k] = T(0);
+      axq[k] = T(0);
       if (qi[k] < m) {
         ok = route[qi[k]] == F_FP32;  // the others are left to the FP64 fix-up
         if (ok) {
           const double D = saved_den[qi[k]];
-          Loader<float, DIM, L>::query(query, qi[k], c);
+          Loader<T, DIM, L>::query(query, qi[k], c);
           zq[k] = saved_z[qi[k]];
           const double g = static_cast<double>(grad_out[qi[k]]);
           if constexpr (REL) {
             double E = 1.0;
-            rel_from_den(D / unit, pd, sg[k], kq[k], E);
-            aq[k] = static_cast<float>(g / E);
-            axq[k] = static_cast<float>(g / E * static_cast<double>(sg[k]));
+            float sgf = 1.f, kqf = 0.f;
+            rel_from_den(D / unit, pd, sgf, kqf, E);
+            sg[k] = sgf;
+            kq[k] = kqf;
+            aq[k] = static_cast<T>(g / E);
+            axq[k] = static_cast<T>(g / E * static_cast<double>(sgf));
           } else {
-            aq[k] = static_cast<float>(g / (D / unit));
+            aq[k] = static_cast<T>(g / (D / unit));
           }
         }
       }
 #pragma unroll
-      for (int d = 0; d < 3; ++d) qc[k][d] = ok ? c[d] * s : kFarF;
+      for (int d = 0; d < 3; ++d) qc[k][d] = ok ? c[d] * s : static_cast<T>(kFarF);
     }
-    float ph[Q], pl[Q], gh[Q][3], gl[Q][3];
+    T ph[Q], pl[Q], gh[Q][3], gl[Q][3];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      ph[k] = pl[k] = 0.f;
+      ph[k] = pl[k] = T(0);
 #pragma unroll
-      for (int d = 0; d < 3; ++d) gh[k][d] = gl[k][d] = 0.f;
+      for (int d = 0; d < 3; ++d) gh[k][d] = gl[k][d] = T(0);
     }
 
     fetch(0);
@@ -227,21 +254,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
       const bool tail = jt + kFTile > je;
 #pragma unroll 1
       for (int b = 0; b < kFBatches; ++b) {
-        float ap[Q], ag[Q][3];
+        T ap[Q], ag[Q][3];
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          ap[k] = 0.f;
-          ag[k][0] = ag[k][1] = ag[k][2] = 0.f;
+          ap[k] = T(0);
+          ag[k][0] = ag[k][1] = ag[k][2] = T(0);
         }
-        const P4<float>* rec = tile[t & 1] + b * (2 * kBatch);
+        const P4<T>* rec = tile[t & 1] + b * (2 * kBatch);
         const int64_t jbat = jt + b * kBatch;
-        float zs, ax[3];
+        T zs, ax[3];
         if (diag || tail)
-          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, NDX, true, 1, REL>(rec, lane, jbat, je, excl, qc, zq, aq, sg, kq,
-                                                                  axq, qi, nhp, ap, ag, ax);
+          zs = bwdf_batch<T, DIM, PM, Q, NDP, NDQ, NDX, true, 1, REL>(rec, lane, jbat, je, excl, qc, zq, aq, sg, kq,
+                                                                     axq, qi, nhp, ap, ag, ax);
         else
-          zs = bwdf_batch<DIM, PM, Q, NDP, NDQ, NDX, false, UNR, REL>(rec, lane, jbat, je, excl, qc, zq, aq, sg,
-                                                                     kq, axq, qi, nhp, ap, ag, ax);
+          zs = bwdf_batch<T, DIM, PM, Q, NDP, NDQ, NDX, false, UNR, REL>(rec, lane, jbat, je, excl, qc, zq, aq, sg,
+                                                                        kq, axq, qi, nhp, ap, ag, ax);
         const int at = b * kBatch + ((lane + kBatch - 1) & (kBatch - 1));
         zred[wave][at] = zs;
         if constexpr (NDX) {
@@ -306,23 +333,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
   }
 }
 
-template <int DIM, int L, int PM, bool REL = false>
+template <typename T, int DIM, int L, int PM, bool REL = false>
 hipError_t launch_bwd_fused_t(const BwdArgs& a, int groups, int ranges, int64_t chunk, hipStream_t st) {
   const bool ndp = (a.flags & 0x4u) != 0, ndq = (a.flags & 0x8u) != 0, ndx = a.part_x != nullptr;
   dim3 grid(static_cast<unsigned>(groups), static_cast<unsigned>(ranges));
-  const float nhp = static_cast<float>(-0.5 * a.p);
-  const float* sz = static_cast<const float*>(a.saved_z);
-  const float* go = static_cast<const float*>(a.grad_out);
-#define IDW_BF(DP, DQ, DX)                                                                               \
-  hipLaunchKernelGGL((k_bwd_fused<DIM, L, PM, 2, DP, DQ, DX, REL>), grid, dim3(kFNT), 0, st, a.data, a.n, \
-                     a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den,              \
-                     a.part_q, a.part_z, a.part_x, a.route, a.p)
+  const T nhp = static_cast<T>(-0.5 * a.p);
+  const T* sz = static_cast<const T*>(a.saved_z);
+  const T* go = static_cast<const T*>(a.grad_out);
+  constexpr int NT = FusedShape<T>::NT;
+#define IDW_BF(DP, DQ, DX)                                                                                  \
+  hipLaunchKernelGGL((k_bwd_fused<T, DIM, L, PM, 2, DP, DQ, DX, REL>), grid, dim3(NT), 0, st, a.data, a.n,    \
+                     a.query, a.m, chunk, groups, nhp, a.flags, a.hdr, sz, go, a.saved_den, a.part_q, a.part_z, \
+                     a.part_x, a.route, a.p)
   // The data-coordinate gradient is instantiated with both query-direction sums (they share
   // its per-pair factors); merges write only what was requested.  With relative weights
-  // every request runs here, dz alone included.
-  if (ndx)
-    IDW_BF(true, true, true);
-  else if (ndp && ndq)
+  // every request runs here, dz alone included.  FP64 takes dz with dp and/or dq only.
+  if constexpr (sizeof(T) == 4) {
+    if (ndx) {
+      IDW_BF(true, true, true);
+      return hipGetLastError();
+    }
+  } else {
+    if (ndx) return hipErrorInvalidValue;
+  }
+  if (ndp && ndq)
     IDW_BF(true, true, false);
   else if (ndp)
     IDW_BF(true, false, false);
@@ -336,17 +370,21 @@ hipError_t launch_bwd_fused_t(const BwdArgs& a, int groups, int ranges, int64_t 
   return hipGetLastError();
 }
 
-template <int DIM, int L>
+template <typename T, int DIM, int L>
 hipError_t bwd_fused_pm(const BwdArgs& a, int groups, int ranges, int64_t chunk, hipStream_t st) {
-  if (a.rel)
-    return a.pmode == PM_GEN ? launch_bwd_fused_t<DIM, L, PM_GEN, true>(a, groups, ranges, chunk, st)
-                             : hipErrorInvalidValue;
+  if constexpr (sizeof(T) == 4) {
+    if (a.rel)
+      return a.pmode == PM_GEN ? launch_bwd_fused_t<T, DIM, L, PM_GEN, true>(a, groups, ranges, chunk, st)
+                               : hipErrorInvalidValue;
+  } else {
+    if (a.rel) return hipErrorInvalidValue;
+  }
   switch (a.pmode) {
-    case PM_1: return launch_bwd_fused_t<DIM, L, PM_1>(a, groups, ranges, chunk, st);
-    case PM_2: return launch_bwd_fused_t<DIM, L, PM_2>(a, groups, ranges, chunk, st);
-    case PM_3: return launch_bwd_fused_t<DIM, L, PM_3>(a, groups, ranges, chunk, st);
-    case PM_4: return launch_bwd_fused_t<DIM, L, PM_4>(a, groups, ranges, chunk, st);
-    default: return launch_bwd_fused_t<DIM, L, PM_GEN>(a, groups, ranges, chunk, st);
+    case PM_1: return launch_bwd_fused_t<T, DIM, L, PM_1>(a, groups, ranges, chunk, st);
+    case PM_2: return launch_bwd_fused_t<T, DIM, L, PM_2>(a, groups, ranges, chunk, st);
+    case PM_3: return launch_bwd_fused_t<T, DIM, L, PM_3>(a, groups, ranges, chunk, st);
+    case PM_4: return launch_bwd_fused_t<T, DIM, L, PM_4>(a, groups, ranges, chunk, st);
+    default: return launch_bwd_fused_t<T, DIM, L, PM_GEN>(a, groups, ranges, chunk, st);
   }
 }
 

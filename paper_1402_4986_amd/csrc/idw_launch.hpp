@@ -132,7 +132,7 @@ constexpr int kCountBlock = 4096; // flags per compaction block (16 per thread)
   hipError_t bwd_data_##NAME(const BwdArgs& a, bool f64, hipStream_t st);        \
   hipError_t bwd_datax_##NAME(const BwdArgs& a, bool f64, hipStream_t st);       \
   hipError_t bwd_fixup_##NAME(const BwdArgs& a, bool f64, hipStream_t st);      \
-  hipError_t bwd_fused_##NAME(const BwdArgs& a, hipStream_t st);                 \
+  hipError_t bwd_fused_##NAME(const BwdArgs& a, bool f64, hipStream_t st);       \
   hipError_t near_check_##NAME(const NearArgs& a, hipStream_t st);              \
   hipError_t grid_##NAME(const GridArgs& a, bool build, hipStream_t st);
 

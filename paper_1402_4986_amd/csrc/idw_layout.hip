@@ -70,9 +70,12 @@ hipError_t IDW_CAT(grid_, IDW_LAYOUT_NAME)(const GridArgs& a, bool build, hipStr
   return launch_grid<IDW_LAYOUT>(a, build, st);
 }
 
-hipError_t IDW_CAT(bwd_fused_, IDW_LAYOUT_NAME)(const BwdArgs& a, hipStream_t st) {
-  return a.dim == 3 ? bwd_fused_pm<3, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st)
-                    : bwd_fused_pm<2, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st);
+hipError_t IDW_CAT(bwd_fused_, IDW_LAYOUT_NAME)(const BwdArgs& a, bool f64, hipStream_t st) {
+  if (f64)
+    return a.dim == 3 ? bwd_fused_pm<double, 3, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st)
+                      : bwd_fused_pm<double, 2, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st);
+  return a.dim == 3 ? bwd_fused_pm<float, 3, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st)
+                    : bwd_fused_pm<float, 2, IDW_LAYOUT>(a, a.fused_groups, a.fused_ranges, a.fused_chunk, st);
 }
 
 }  // namespace idw

@@ -117,8 +117,8 @@ typedef struct idw_points {
  *                     separately instead of the fused sweep (same results within the
  *                     stated tolerances; for comparison).  These sweeps use the direct
  *                     weights at every p (see "Large p in FP32").  The fused sweep serves
- *                     FP32 requests with dz and dp/dq, with dx, or (p >= 6) any request,
- *                     and FP64 requests with dz and dp/dq but no dx.
+ *                     requests with dz and dp/dq, or with dx, and in FP32 with p >= 6 any
+ *                     request.
  *   near_search       nearest-distance searches (the near-coincidence check of candidate
  *                     queries, and the nearest distance every query needs for the relative
  *                     weights of p >= 6): 0 = a uniform grid over the data points, built in

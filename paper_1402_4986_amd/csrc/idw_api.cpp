@@ -663,12 +663,10 @@ int idw_backward(const idw_points* data, const idw_points* query, double p, int3
                       "near-coincidence check")))
     return rc;
   a.route = flag;
-  // The fused sweep pays off when both directions are needed: dz with dp or dq; in FP32
-  // also dx (alone or with the others: its per-pair factors are those of dq).  FP64 runs
-  // dx through the separate sweeps.
-  const bool both = ndz && (ndp || ndq);
-  const bool fused = rel || (w.fused_groups > 0 && !separate && (f64 ? (both && !ndx) : (ndx || both)));
-  if (fused) {  // one sweep for dp/dq and dz (and, in FP32, dx)
+  // The fused sweep pays off when both directions are needed: dz with dp or dq, or dx
+  // (alone or with the others: its per-pair factors are those of dq).
+  const bool fused = rel || (w.fused_groups > 0 && !separate && (ndx || (ndz && (ndp || ndq))));
+  if (fused) {  // one sweep for dp/dq and dz (and dx)
     a.fused_groups = w.fused_groups;
     a.fused_ranges = w.fused_ranges;
     a.fused_chunk = w.fused_chunk;

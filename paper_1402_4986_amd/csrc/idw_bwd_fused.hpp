@@ -142,9 +142,8 @@ constexpr int kFNT = FusedShape<float>::NT;
 // pair terms finite, so that their zero factors a = 0 give exact zeros.
 constexpr float kFarF = 0x1p60f;
 
-// T = float: the FP32 adjoint (with relative weights for large p, and the data-coordinate
-// sums); T = double: the FP64 adjoint of dz with dp and/or dq (the FP64 one-step and table
-// forms of the weights, no relative weights, no data-coordinate sums).
+// T = float: the FP32 adjoint (with relative weights for large p); T = double: the FP64
+// adjoint (the FP64 one-step and table forms of the weights, no relative weights).
 template <typename T, int DIM, int L, int PM, int Q, bool NDP, bool NDQ, bool NDX, bool REL = false, int UNR = 2,
           int WPE = 2, int NT = FusedShape<T>::NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_bwd_fused(
@@ -152,7 +151,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
     const double* __restrict__ hdr, const T* __restrict__ saved_z, const T* __restrict__ grad_out,
     const double* __restrict__ saved_den, double4* __restrict__ part_q, double* __restrict__ part_z,
     double* __restrict__ part_x, const uint8_t* __restrict__ route, double pd) {
-  static_assert(sizeof(T) == 4 || (!REL && !NDX), "FP64: no relative weights, no data-coordinate sums");
+  static_assert(sizeof(T) == 4 || !REL, "FP64: no relative weights");
   constexpr int kFTile = FusedShape<T>::TILE;
   constexpr int kFBatches = kFTile / kBatch;
   __shared__ P4<T> tile[2][2 * kFTile];   // batches stored twice in a row
@@ -347,16 +346,10 @@ hipError_t launch_bwd_fused_t(const BwdArgs& a, int groups, int ranges, int64_t 
                      a.part_x, a.route, a.p)
   // The data-coordinate gradient is instantiated with both query-direction sums (they share
   // its per-pair factors); merges write only what was requested.  With relative weights
-  // every request runs here, dz alone included.  FP64 takes dz with dp and/or dq only.
-  if constexpr (sizeof(T) == 4) {
-    if (ndx) {
-      IDW_BF(true, true, true);
-      return hipGetLastError();
-    }
-  } else {
-    if (ndx) return hipErrorInvalidValue;
-  }
-  if (ndp && ndq)
+  // every request runs here, dz alone included.
+  if (ndx)
+    IDW_BF(true, true, true);
+  else if (ndp && ndq)
     IDW_BF(true, true, false);
   else if (ndp)
     IDW_BF(true, false, false);

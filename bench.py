@@ -259,7 +259,21 @@ def main():
                 torch.cuda.synchronize()
                 lay[prec][layout] = round(e0.elapsed_time(e1) / 2, 3)
                 del d2, q2
-        del Z64
+        # the FP64 adjoint (dz, dp, dq) of the same problem, aligned-AoS records
+        d64, q64 = make("aoas", "f64")
+        g64 = torch.tensor(g, dtype=torch.float64, device=dev)
+        ws64 = api.workspace(d64, q64, "f64")
+        api.forward(d64, q64, p, "f64", out_z=Z64, out_den=D, ws=ws64)
+        api.backward(d64, q64, p, g64, Z64, D, "f64", ws=ws64)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2):
+            api.backward(d64, q64, p, g64, Z64, D, "f64", ws=ws64)
+        e1.record()
+        torch.cuda.synchronize()
+        out["adjoint_ms_f64"] = round(e0.elapsed_time(e1) / 2, 3)
+        del d64, q64, g64, Z64, ws64
         out["forward_ms_by_layout"] = lay
         # the per-pair Kahan variant of the FP32 forward, same records
         api.forward(data, query, p, "f32_kahan", out_z=Z, out_den=D, ws=ws)

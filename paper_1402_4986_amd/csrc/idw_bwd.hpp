@@ -31,14 +31,21 @@
 
 namespace idw {
 
-// w, a factor f with w / r2 = w * f (when the position gradient is needed), and log2(r2)
-// (when the power gradient is needed), in the cheapest form for the weight class.
+// w, a factor f for w / r2 (when the position gradient is needed), and log2(r2) (when the
+// power gradient is needed), in the cheapest form for the weight class.  For the fast
+// classes f = 1/r2 (w / r2 = w f); for general p f = w / r2 itself, taken as
+// 2^((-p/2 - 1) log2 r2) with w = f r2, which spares a reciprocal.  wr_times forms
+// (w / r2) c from either.
 template <int PM, bool NDQ, bool NDP>
 __device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& f, float& lg) {
   if constexpr (PM == PM_GEN) {
     lg = __builtin_amdgcn_logf(r2);
-    w = __builtin_amdgcn_exp2f(nhp * lg);
-    if constexpr (NDQ) f = __builtin_amdgcn_rcpf(r2);
+    if constexpr (NDQ) {
+      f = __builtin_amdgcn_exp2f((nhp - 1.0f) * lg);
+      w = f * r2;
+    } else {
+      w = __builtin_amdgcn_exp2f(nhp * lg);
+    }
   } else {
     if constexpr (NDP) lg = __builtin_amdgcn_logf(r2);
     if constexpr (PM == PM_2) {
@@ -68,9 +75,13 @@ __device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& f, 
 template <int PM, bool NDQ, bool NDP>
 __device__ __forceinline__ void wterms(double r2, double nhp, double& w, double& f, double& lg) {
   if constexpr (NDP || PM == PM_GEN) lg = log2_t(r2);  // log2_table_init in the kernel
-  if constexpr (PM == PM_GEN) {
-    w = exp2_t(nhp * lg);  // exp2_table_init in the kernel
-    if constexpr (NDQ) f = rcp64_w(r2);
+  if constexpr (PM == PM_GEN) {  // exp2_table_init in the kernel
+    if constexpr (NDQ) {
+      f = exp2_t((nhp - 1.0) * lg);
+      w = f * r2;
+    } else {
+      w = exp2_t(nhp * lg);
+    }
   } else if constexpr (PM == PM_2) {
     w = rcp64_w(r2);
     if constexpr (NDQ) f = w;
@@ -82,6 +93,15 @@ __device__ __forceinline__ void wterms(double r2, double nhp, double& w, double&
     w = weight_sweep<PM>(r2, nhp);
     if constexpr (NDQ) f = rcp64_w(r2);
   }
+}
+
+// (w / r2) c from t = w c and wterms' factor f.
+template <int PM, typename T>
+__device__ __forceinline__ T wr_times(T t, T c, T f) {
+  if constexpr (PM == PM_GEN)
+    return f * c;
+  else
+    return t * f;
 }
 
 // One LDS tile of the query sweep.  `cnt` records are valid (all of them unless TAIL).
@@ -127,7 +147,7 @@ __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt,
         const T t = w * c;
         if constexpr (NDP) ap[k] = fmaT(t, lg, ap[k]);
         if constexpr (NDQ) {
-          const T u = t * f;  // (w / r2) (z - Z)
+          const T u = wr_times<PM>(t, c, f);  // (w / r2) (z - Z)
           ag[k][0] = fmaT(u, dx, ag[k][0]);
           ag[k][1] = fmaT(u, dy, ag[k][1]);
           if constexpr (DIM == 3) ag[k][2] = fmaT(u, dz, ag[k][2]);
@@ -548,7 +568,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
           wterms<PM, true, false>(r2, nhp, w, f, lg);
           const T aw = aa * w;
           az[k] += aw;
-          const T v = aw * f * (xv[k] - zi);
+          const T v = wr_times<PM>(aw, aa, f) * (xv[k] - zi);
           ax[k][0] = fmaT(v, e0, ax[k][0]);
           ax[k][1] = fmaT(v, e1, ax[k][1]);
           if constexpr (DIM == 3) ax[k][2] = fmaT(v, e2, ax[k][2]);

@@ -108,7 +108,7 @@ __device__ __forceinline__ T bwdf_batch(const P4<T>* __restrict__ rec, int lane,
       const T t = w * c;
       if constexpr (NDP) ap[k] = fmaT(t, lg, ap[k]);
       if constexpr (NDQ || NDX) {
-        const T u = t * f;  // (w / r2)(z - Z)
+        const T u = wr_times<PM>(t, c, f);  // (w / r2)(z - Z)
         if constexpr (NDQ) {
           ag[k][0] = fmaT(u, dx, ag[k][0]);
           ag[k][1] = fmaT(u, dy, ag[k][1]);

@@ -408,8 +408,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 
   const int ntiles = static_cast<int>((ie - ib + kTile - 1) / kTile);
   const bool excl = (flags & 1u) != 0;
-  if constexpr (sizeof(T) == 8 && PM == PM_GEN) log2_table_init();  // FP64 log2 (synchronised below)
-  if constexpr (sizeof(T) == 8 && PM == PM_GEN) exp2_table_init();
+  if constexpr (sizeof(T) == 8 && PM == PM_GEN) pow_table_init(nhp);  // FP64 weight tables (synchronised below)
   fetch(0);
   put(0);
   __syncthreads();

@@ -284,6 +284,69 @@ __device__ __forceinline__ double exp2_t(double x) {
   return x == __builtin_huge_val() ? x : r;
 }
 
+// The general-p weight a^nh (nh = -p/2) in the FP64 sweeps that need no log2 (forward, data
+// sweep), from two tables filled per call: a = 2^e m, m in [1, 2), k = top 8 mantissa bits;
+// m = (1 + r) / i_k with i_k the rounded 1/c_k, c_k = 1 + (k + 1/2)/256, |r| <= 2^-9; so
+// a^nh = [2^(e nh)] [i_k^(-nh)] (1 + r)^nh, the first two factors from the tables (2048 and
+// 256 entries, library exp2 and pow) and the last as its binomial series through r^10
+// (truncation below 2^-66 for |nh| <= 32).  Against exp2_t(nh log2_t(a)) the FP64 forward's
+// inner loop drops from about 50 to 33 instructions a pair (29 to 19 of them FP64), and the
+// rounding no longer grows with |nh log2 a|.  Zero and subnormal a give +inf (exact or
+// near-coincident hits, settled by the FP64 fix-up).
+constexpr int kPowExp = 2048;
+
+__device__ __forceinline__ double* pow_etable() {
+  __shared__ double tab[kPowExp];
+  return tab;
+}
+__device__ __forceinline__ double2* pow_mtable() {
+  __shared__ double2 tab[kLogTab];
+  return tab;
+}
+__device__ __forceinline__ double* pow_coef() {
+  __shared__ double c[12];
+  return c;
+}
+
+__device__ __forceinline__ void pow_table_init(double nh) {
+  for (int i = threadIdx.x; i < kPowExp; i += blockDim.x) {
+    // 2^(e nh) with the product e nh split exactly (hi + lo), so that its rounding does not
+    // grow with |e nh|; the last entry (a = +inf) gives weight 0.
+    const double e = static_cast<double>(i - 1023);
+    const double hi = e * nh;
+    const double lo = fma(e, nh, -hi);
+    pow_etable()[i] = i < kPowExp - 1 ? exp2(hi) * fma(lo, 0.69314718055994530942, 1.0) : 0.0;
+  }
+  for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) {
+    const double inv = 1.0 / (1.0 + (k + 0.5) / kLogTab);
+    pow_mtable()[k] = make_double2(inv, pow(inv, -nh));
+  }
+  if (threadIdx.x == 0) {  // binomial coefficients C(nh, j), j = 0..10
+    double c = 1.0;
+    pow_coef()[0] = 1.0;
+    for (int j = 1; j <= 10; ++j) {
+      c = c * (nh - (j - 1)) / j;
+      pow_coef()[j] = c;
+    }
+  }
+}
+
+__device__ __forceinline__ double pow_t(double a) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, a);
+  const unsigned int hi = static_cast<unsigned int>(b >> 32);
+  const int k = static_cast<int>((hi >> 12) & (kLogTab - 1));
+  const int ei = static_cast<int>((hi >> 20) & 0x7ff);
+  const double m = __builtin_bit_cast(double, (b & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
+  const double2 t = pow_mtable()[k];
+  const double r = fma(m, t.x, -1.0);
+  const double* c = pow_coef();
+  double q = c[10];
+#pragma unroll
+  for (int j = 9; j >= 0; --j) q = fma(q, r, c[j]);
+  const double res = pow_etable()[ei] * t.y * q;
+  return a >= 0x1p-1022 ? res : __builtin_huge_val();
+}
+
 // Coordinate of padding records in the sweeps' LDS tiles: +inf in FP32 (every weight form
 // gives exactly 0 there), a far finite value in FP64 (weights of about 2^-800 and below,
 // which the one-step forms above handle).
@@ -320,8 +383,8 @@ __device__ __forceinline__ double weight_sweep(double r2, double nhp) {
   } else if constexpr (PM == PM_25) {
     const double s = rsq64_w(r2);
     return s * s * sqrt(s);
-  } else {  // general p: the table log2 and exp2 (their *_table_init in the calling kernel)
-    return exp2_t(nhp * log2_t(r2));
+  } else {  // general p: the tables of pow_t (pow_table_init in the calling kernel)
+    return pow_t(r2);
   }
 }
 

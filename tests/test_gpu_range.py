@@ -113,3 +113,32 @@ def test_batched_large_exponent_and_values():
         assert np.all(np.isfinite(Zg))
         assert np.max(scaled_err(Zg, ref)) <= TOL["f32"], p
     plan.close()
+
+
+# The FP64 sweeps take a general-p weight as 2^(e nh) from an exponent table times a
+# mantissa table entry and a short series.  The FP64 path does not rescale the coordinates,
+# so factors of 1e-90 and 1e90 put r^2 hundreds of binades away from 1, far into the
+# exponent table; p near 64 stresses the series.  The forward and the dz-only adjoint (the
+# data sweep) both run through those weights; few queries may take the FP64 fix-up.
+@pytest.mark.parametrize("scale,p", [(1e-90, 2.9), (1.0, 0.37), (1.0, 17.9), (1.0, 63.5),
+                                     (1e90, 1.3)])
+def test_f64_general_p_across_scales(scale, p):
+    x, z, q = rand_case(71, 3000, 1000, 2, "f64")
+    x, q = x * scale, q * scale
+    q[:4] = x[:4]                                   # exact hits
+    g = np.random.default_rng(72).normal(size=len(q))
+    print(f"case scale={scale} p={p}", flush=True)
+    ref = oracle.forward(x, z, q, p)
+    assert np.all(np.isfinite(ref["Z"])) and np.all(np.isfinite(ref["D"][4:]))
+    d, qq = points(x, z, q, "aoas", "f64")
+    ws = api.workspace(d, qq, "f64")
+    Z, D = api.forward(d, qq, p, "f64", ws=ws)
+    torch.cuda.synchronize()
+    nf = int(ws[256:260].view(torch.int32).item())
+    assert nf <= 4 + len(q) // 100, f"{nf} queries took the FP64 fix-up"
+    assert np.max(scaled_err(Z.cpu().numpy(), ref)) <= TOL["f64"]
+    dz, _, _ = api.backward(d, qq, p, torch.as_tensor(g, device="cuda"), Z, D, "f64", ws=ws,
+                            need_dp=False, need_dq=False)
+    gref = oracle.backward(x, z, q, p, g)
+    e = np.abs(dz.cpu().numpy() - gref["dz"]) / gref["dz_scale"]
+    assert np.max(e) <= GTOL["f64"], f"dz err {np.max(e):.3e}"

@@ -35,8 +35,9 @@ namespace idw {
 // power gradient is needed), in the cheapest form for the weight class.  For the fast
 // classes f = 1/r2 (w / r2 = w f); for general p f = w / r2 itself, taken as
 // 2^((-p/2 - 1) log2 r2) with w = f r2, which spares a reciprocal.  wr_times forms
-// (w / r2) c from either.
-template <int PM, bool NDQ, bool NDP>
+// (w / r2) c from either.  POW (FP64, general p, no dp) takes the weight or w / r2 from the
+// tables of pow_t instead: the kernel fills them for the exponent nh - 1 when NDQ, else nh.
+template <int PM, bool NDQ, bool NDP, bool POW = false>
 __device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& f, float& lg) {
   if constexpr (PM == PM_GEN) {
     lg = __builtin_amdgcn_logf(r2);
@@ -72,8 +73,19 @@ __device__ __forceinline__ void wterms(float r2, float nhp, float& w, float& f, 
   }
 }
 
-template <int PM, bool NDQ, bool NDP>
+template <int PM, bool NDQ, bool NDP, bool POW = false>
 __device__ __forceinline__ void wterms(double r2, double nhp, double& w, double& f, double& lg) {
+  static_assert(!POW || (PM == PM_GEN && !NDP), "the pow tables serve general p without dp");
+  if constexpr (POW) {  // pow_table_init in the kernel
+    const double g = pow_t(r2);
+    if constexpr (NDQ) {
+      f = g;
+      w = g * r2;
+    } else {
+      w = g;
+    }
+    return;
+  }
   if constexpr (NDP || PM == PM_GEN) lg = log2_t(r2);  // log2_table_init in the kernel
   if constexpr (PM == PM_GEN) {  // exp2_table_init in the kernel
     if constexpr (NDQ) {
@@ -94,6 +106,14 @@ __device__ __forceinline__ void wterms(double r2, double nhp, double& w, double&
     if constexpr (NDQ) f = rcp64_w(r2);
   }
 }
+
+// Whether an FP64 sweep takes its general-p weights from the pow_t tables: only without dp
+// (whose log2 r2 the exp2/log2 route shares; a combined log2 and pow measured slower there,
+// its registers and LDS costing occupancy).
+template <typename T, int PM, bool NDP>
+struct PowTab {
+  static constexpr bool on = sizeof(T) == 8 && PM == PM_GEN && !NDP;
+};
 
 // (w / r2) c from t = w c and wterms' factor f.
 template <int PM, typename T>
@@ -143,7 +163,7 @@ __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt,
           }
         }
         T w, f = T(0), lg = T(0);
-        wterms<PM, NDQ, NDP>(r2, nhp, w, f, lg);
+        wterms<PM, NDQ, NDP, PowTab<T, PM, NDP>::on>(r2, nhp, w, f, lg);
         const T t = w * c;
         if constexpr (NDP) ap[k] = fmaT(t, lg, ap[k]);
         if constexpr (NDQ) {
@@ -227,8 +247,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 
   const int ntiles = static_cast<int>((je - jb + kTile - 1) / kTile);
   const bool excl = (flags & 1u) != 0;
-  if constexpr (sizeof(T) == 8 && (PM == PM_GEN || NDP)) log2_table_init();  // FP64 log2 (synchronised below)
-  if constexpr (sizeof(T) == 8 && PM == PM_GEN) exp2_table_init();
+  constexpr bool kPow = PowTab<T, PM, NDP>::on;
+  if constexpr (kPow) pow_table_init(NDQ ? nhp - 1.0 : nhp);  // FP64 tables (synchronised below)
+  if constexpr (sizeof(T) == 8 && !kPow && (PM == PM_GEN || NDP)) log2_table_init();
+  if constexpr (sizeof(T) == 8 && !kPow && PM == PM_GEN) exp2_table_init();
   fetch(0);
   put(0);
   __syncthreads();

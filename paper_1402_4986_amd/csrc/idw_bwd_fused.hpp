@@ -103,7 +103,7 @@ __device__ __forceinline__ T bwdf_batch(const P4<T>* __restrict__ rec, int lane,
         }
       }
       T w, f = T(0), lg = T(0);
-      wterms<PM, NDQ || NDX, NDP>(r2, nhp, w, f, lg);
+      wterms<PM, NDQ || NDX, NDP, PowTab<T, PM, NDP || NDX>::on>(r2, nhp, w, f, lg);
       if constexpr (REL && NDP) lg -= kq[k];
       const T t = w * c;
       if constexpr (NDP) ap[k] = fmaT(t, lg, ap[k]);
@@ -168,8 +168,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
   const T s = static_cast<T>(hdr[H_SCALE]);
   const double unit = hdr[H_DEN_UNIT];
   const bool excl = (flags & 1u) != 0;
-  if constexpr (sizeof(T) == 8 && (NDP || PM == PM_GEN)) log2_table_init();  // synchronised below
-  if constexpr (sizeof(T) == 8 && PM == PM_GEN) exp2_table_init();
+  // FP64 tables (synchronised below); with dx the pow tables cost too much occupancy.
+  constexpr bool kPow = PowTab<T, PM, NDP || NDX>::on;
+  if constexpr (kPow) pow_table_init(NDQ ? nhp - 1.0 : nhp);
+  if constexpr (sizeof(T) == 8 && !kPow && (NDP || PM == PM_GEN)) log2_table_init();
+  if constexpr (sizeof(T) == 8 && !kPow && PM == PM_GEN) exp2_table_init();
   const int64_t qpb = static_cast<int64_t>(NT) * Q;
   const int64_t nqb = (m + qpb - 1) / qpb;
   const int ntiles = static_cast<int>((je - jb + kFTile - 1) / kFTile);

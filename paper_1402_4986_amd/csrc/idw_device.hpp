@@ -285,11 +285,12 @@ __device__ __forceinline__ double exp2_t(double x) {
 }
 
 // The general-p weight a^nh (nh = -p/2) in the FP64 sweeps that need no log2 (forward, data
-// sweep), from two tables filled per call: a = 2^e m, m in [1, 2), k = top 8 mantissa bits;
+// sweep; in the adjoint sweeps without dp, w / r2 = a^(nh - 1) the same way, nh - 1 standing
+// for nh below), from two tables filled per call: a = 2^e m, m in [1, 2), k = top 8 bits;
 // m = (1 + r) / i_k with i_k the rounded 1/c_k, c_k = 1 + (k + 1/2)/256, |r| <= 2^-9; so
 // a^nh = [2^(e nh)] [i_k^(-nh)] (1 + r)^nh, the first two factors from the tables (2048 and
 // 256 entries, library exp2 and pow) and the last as its binomial series through r^10
-// (truncation below 2^-66 for |nh| <= 32).  Against exp2_t(nh log2_t(a)) the FP64 forward's
+// (truncation below 2^-66 for |nh| <= 33).  Against exp2_t(nh log2_t(a)) the FP64 forward's
 // inner loop drops from about 50 to 33 instructions a pair (29 to 19 of them FP64), and the
 // rounding no longer grows with |nh log2 a|.  Zero and subnormal a give +inf (exact or
 // near-coincident hits, settled by the FP64 fix-up).

@@ -117,10 +117,14 @@ def test_batched_large_exponent_and_values():
 
 # The FP64 sweeps take a general-p weight as 2^(e nh) from an exponent table times a
 # mantissa table entry and a short series.  The FP64 path does not rescale the coordinates,
-# so factors of 1e-90 and 1e90 put r^2 hundreds of binades away from 1, far into the
-# exponent table; p near 64 stresses the series.  The forward and the dz-only adjoint (the
-# data sweep) both run through those weights; few queries may take the FP64 fix-up.
-@pytest.mark.parametrize("scale,p", [(1e-90, 2.9), (1.0, 0.37), (1.0, 17.9), (1.0, 63.5),
+# so factors of 1e-40 and 1e90 put r^2 hundreds of binades away from 1, far into the
+# exponent table; p near 64 stresses the series.  (The adjoint's factor w / r^2 =
+# (r^2)^(-p/2 - 1) must itself stay within the FP64 range: at 1e-90 and p = 2.9 it would
+# reach 1e441.)  The forward, the dz-only adjoint (the data
+# sweep), the dz + dq adjoint (fused, w / r^2 from the tables) and dq alone (the query sweep)
+# run through those weights;
+# few queries may take the FP64 fix-up.
+@pytest.mark.parametrize("scale,p", [(1e-40, 2.9), (1.0, 0.37), (1.0, 17.9), (1.0, 63.5),
                                      (1e90, 1.3)])
 def test_f64_general_p_across_scales(scale, p):
     x, z, q = rand_case(71, 3000, 1000, 2, "f64")
@@ -142,3 +146,13 @@ def test_f64_general_p_across_scales(scale, p):
     gref = oracle.backward(x, z, q, p, g)
     e = np.abs(dz.cpu().numpy() - gref["dz"]) / gref["dz_scale"]
     assert np.max(e) <= GTOL["f64"], f"dz err {np.max(e):.3e}"
+    dz, _, dq = api.backward(d, qq, p, torch.as_tensor(g, device="cuda"), Z, D, "f64", ws=ws,
+                             need_dp=False)
+    e = np.abs(dz.cpu().numpy() - gref["dz"]) / gref["dz_scale"]
+    assert np.max(e) <= GTOL["f64"], f"dz (with dq) err {np.max(e):.3e}"
+    e = np.max(np.abs(dq.cpu().numpy() - gref["dq"])[4:], axis=1) / gref["dq_cond"][4:]
+    assert np.max(e) <= GTOL["f64"], f"dq err {np.max(e):.3e}"      # rows 0-3: exact hits
+    _, _, dq = api.backward(d, qq, p, torch.as_tensor(g, device="cuda"), Z, D, "f64", ws=ws,
+                            need_dz=False, need_dp=False)    # the query sweep alone
+    e = np.max(np.abs(dq.cpu().numpy() - gref["dq"])[4:], axis=1) / gref["dq_cond"][4:]
+    assert np.max(e) <= GTOL["f64"], f"dq (alone) err {np.max(e):.3e}"

@@ -158,6 +158,28 @@ def test_scale_bounds_the_result():
     assert np.all(out["Z"] >= z.min() - 1e-15) and np.all(out["Z"] <= z.max() + 1e-15)
 
 
+def test_scale_equals_the_result_for_nonnegative_values_and_two_point_form():
+    # S = sum w |z| / sum w: with every z >= 0 its sum is the numerator's, term by term, so
+    # S equals Z bit for bit; at a hit it is |Z|.  On two points with values of both signs it
+    # has the closed form (|z0| d1^p + |z1| d0^p) / (d0^p + d1^p).  (S is the denominator of
+    # every forward tolerance, so it is pinned from above as well as below.)
+    r = _rng(8)
+    x = r.random((90, 2))
+    z = np.abs(r.normal(size=90))
+    q = r.random((30, 2))
+    q[0] = x[5]
+    out = oracle.forward(x, z, q, 1.7)
+    np.testing.assert_array_equal(out["S"], out["Z"])
+    x2 = np.array([[0.3, 0.1], [-0.2, 0.6]])
+    z2 = np.array([1.5, -2.0])
+    q2 = np.array([[0.05, 0.2]])
+    d0, d1 = np.linalg.norm(x2 - q2, axis=1)
+    for p in (1.0, 2.5):
+        out = oracle.forward(x2, z2, q2, p)
+        want = (abs(z2[0]) * d1 ** p + abs(z2[1]) * d0 ** p) / (d0 ** p + d1 ** p)
+        assert out["S"][0] == pytest.approx(want, rel=1e-14)
+
+
 def test_bad_arguments_are_rejected():
     x = np.zeros((3, 2))
     with pytest.raises(ValueError):

@@ -68,6 +68,54 @@ def test_scales_bound_gradients():
     assert an["dp_scale"] <= an["dp_cond"] * (1 + 1e-14)
 
 
+def test_value_scale_equals_the_value_gradient_for_nonnegative_upstream():
+    # dz_scale_j = sum_i |g_i| w_ij / D_i (1/h at a hit): with every g_i >= 0 its terms are
+    # those of dz_j, added in the same order, so the two are equal bit for bit.  A stray
+    # factor in the scale, which would loosen every dz tolerance, fails here.
+    x, z, q, g = _case(28, n=60, m=15, dim=3, hit=True)
+    x[9] = x[2]                      # the hit query meets a duplicated point
+    g = np.abs(g)
+    an = oracle.backward(x, z, q, 2.5, g)
+    np.testing.assert_array_equal(an["dz_scale"], an["dz"])
+
+
+def test_centred_scales_equal_the_gradients_when_every_term_has_one_sign():
+    # q at the origin, x1 = (-1/2, 0) with z1 = 1, x2 = (2, 0) with z2 = 0, g > 0.  Z lies
+    # strictly between z2 and z1, so z1 - Z > 0 > z2 - Z; ln r2 is ln(1/4) < 0 for x1 and
+    # ln 4 > 0 for x2; q - x is +1/2 and -2 along x and 0 along y.  Every term of the power
+    # sum w ln(r2)(z - Z) is then negative and every term of the position sum
+    # (w / r2)(z - Z)(q - x) positive, so the centred scales (sums of absolute terms) equal
+    # |dp| and |dq_x| exactly.
+    x = np.array([[-0.5, 0.0], [2.0, 0.0]])
+    z = np.array([1.0, 0.0])
+    q = np.array([[0.0, 0.0]])
+    for p in (1.0, 2.0, 2.5):
+        an = oracle.backward(x, z, q, p, np.array([0.8]))
+        assert an["dp"] > 0 and an["dp_scale"] == an["dp"]
+        assert an["dq"][0, 1] == 0.0
+        assert an["dq_scale"][0] == abs(an["dq"][0, 0])
+
+
+@pytest.mark.parametrize("p", [1.0, 2.5])
+def test_condition_scales_closed_form_on_a_constant_field(p):
+    # Four points at distance h around q (on the axes), every value c: Z = c, D = 4 h^-p.
+    # The uncentred sums take |z_j| + |Z| = 2|c| for every term:
+    #   dq_cond = |p g / D| * 4 (h^-p / h^2) 2|c| h = 2 p |g| |c| / h,
+    #   dp_cond = |g / D| * 4 h^-p |ln h| 2|c|    = 2 |g| |c| |ln h|,
+    #   dx_cond_j = |p g / D| (h^-p / h^2) 2|c| h = p |g| |c| / (2 h)  for each point,
+    # while the centred dq and dp scales vanish (z - Z = 0).
+    h, c, g = 0.375, -1.25, 0.6
+    qc = np.array([0.3, -0.1])
+    x = qc + np.array([[h, 0.0], [-h, 0.0], [0.0, h], [0.0, -h]])
+    z = np.full(4, c)
+    an = oracle.backward(x, z, qc[None, :], p, np.array([g]))
+    assert an["dq_cond"][0] == pytest.approx(2 * p * abs(g) * abs(c) / h, rel=1e-14)
+    assert an["dp_cond"] == pytest.approx(2 * abs(g) * abs(c) * abs(np.log(h)), rel=1e-14)
+    assert an["dq_scale"][0] == 0.0 and an["dp_scale"] == 0.0
+    ax = oracle.backward_x(x, z, qc[None, :], p, np.array([g]))
+    np.testing.assert_allclose(ax["dx_cond"], p * abs(g) * abs(c) / (2 * h), rtol=1e-14)
+
+
 def test_leave_one_out_equals_explicit_deletion():
     r = np.random.default_rng(25)
     n = 48

@@ -4,8 +4,9 @@ difference), builds it with gcc in a temporary directory, and checks that the pi
 below rejects it, while the unmodified oracle passes the same battery.
 
 The battery restates pins from the other oracle tests (closed forms, exact hits, decimal
-brute force of the forward, 80-digit finite differences of every gradient, the dz sum rule)
-so that one failure anywhere fails the battery."""
+brute force of the forward, 80-digit finite differences of every gradient, the dz sum rule,
+and the condition scales pinned from above: equal to what they bound where every term has
+one sign, closed forms on a constant field) so that one failure anywhere fails it."""
 import os
 
 import numpy as np
@@ -27,6 +28,17 @@ MUTANTS = [
     ("dq difference flipped", "double dk = qi[k] - xj[k];", "double dk = xj[k] - qi[k];"),
     ("dx difference flipped", "const double e = qi[k] - xj[k];", "const double e = xj[k] - qi[k];"),
     ("dz without 1/D", "nadd(&dzs[j], gi * w / Di);", "nadd(&dzs[j], gi * w);"),
+    # the condition scales, denominators of every parity tolerance: a stray factor in any of
+    # them would loosen the GPU tests while every other pin still passed
+    ("forward scale doubled", "nadd(&sab, w * fabs(z[j]));", "nadd(&sab, 2.0 * w * fabs(z[j]));"),
+    ("dz scale doubled", "nadd(&dza[j], fabs(gi) * w / Di);", "nadd(&dza[j], 2.0 * fabs(gi) * w / Di);"),
+    ("dp scale doubled", "nadd(&Pa, fabs(lp));", "nadd(&Pa, 2.0 * fabs(lp));"),
+    ("dp condition doubled", "nadd(&Pc, fabs(w * 0.5 * log(r2)) * cabs);",
+     "nadd(&Pc, 2.0 * fabs(w * 0.5 * log(r2)) * cabs);"),
+    ("dq scale doubled", "nadd(&Ga, fabs(u) * ua);", "nadd(&Ga, 2.0 * fabs(u) * ua);"),
+    ("dq condition doubled", "nadd(&Gc, (w / r2) * cabs * ua);", "nadd(&Gc, 2.0 * (w / r2) * cabs * ua);"),
+    ("dx condition doubled", "nadd(&cnd[j], fabs(a) * f * (fabs(z[j]) + fabs(Zi)) * ea);",
+     "nadd(&cnd[j], 2.0 * fabs(a) * f * (fabs(z[j]) + fabs(Zi)) * ea);"),
 ]
 
 
@@ -81,6 +93,26 @@ def _battery(lib):
     gb = r.normal(size=12)
     bb = oracle.backward(xb, r.normal(size=50), r.random((12, 2)), 2.0, gb, lib=lib)
     assert np.sum(bb["dz"]) == pytest.approx(np.sum(gb), rel=1e-13)
+    # the condition scales from above: equal to the quantity they bound where every term
+    # has one sign, and closed forms on a constant field (four points at distance h)
+    zp = np.abs(r.normal(size=50))
+    qp = r.random((12, 2))
+    qp[0] = xb[3]
+    out = oracle.forward(xb, zp, qp, 1.7, lib=lib)
+    np.testing.assert_array_equal(out["S"], out["Z"])
+    bp = oracle.backward(xb, zp, qp, 1.7, np.abs(gb), lib=lib)
+    np.testing.assert_array_equal(bp["dz_scale"], bp["dz"])
+    bs = oracle.backward(np.array([[-0.5, 0.0], [2.0, 0.0]]), np.array([1.0, 0.0]), np.zeros((1, 2)), 2.0,
+                         np.array([0.8]), lib=lib)
+    assert bs["dp_scale"] == bs["dp"] and bs["dq_scale"][0] == abs(bs["dq"][0, 0])
+    h, cv, gv, pv = 0.375, -1.25, 0.6, 2.5
+    qc = np.array([[0.3, -0.1]])
+    xc = qc + np.array([[h, 0.0], [-h, 0.0], [0.0, h], [0.0, -h]])
+    bc = oracle.backward(xc, np.full(4, cv), qc, pv, np.array([gv]), lib=lib)
+    assert bc["dq_cond"][0] == pytest.approx(2 * pv * gv * abs(cv) / h, rel=1e-14)
+    assert bc["dp_cond"] == pytest.approx(2 * gv * abs(cv) * abs(np.log(h)), rel=1e-14)
+    xcnd = oracle.backward_x(xc, np.full(4, cv), qc, pv, np.array([gv]), lib=lib)["dx_cond"]
+    np.testing.assert_allclose(xcnd, pv * gv * abs(cv) / (2 * h), rtol=1e-14)
 
 
 def test_unmodified_oracle_passes_the_battery():

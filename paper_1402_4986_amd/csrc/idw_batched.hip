@@ -266,7 +266,7 @@ __device__ __forceinline__ void kb_item(const BInst& I, const BItem& it, const d
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) fetch(t + 1);
-    fwd_tile<float, DIM, PM, kBQ, false, 4, false, REL>(tile[t & 1], 0, qc, qi, I.nhp, sg, nh, nl, dh, dl);
+    fwd_tile<float, DIM, PM, kBQ, false, 4, false, REL>(tile[t & 1], 0, kTile, qc, qi, I.nhp, sg, nh, nl, dh, dl);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }

@@ -730,7 +730,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_fix1_merge(const int* __restrict__ 
   const int cnt = *count;
   const int C = fix_chunks(cnt, cmax);
   if (C <= 1) return;
-  for (int sl = blockIdx.x * kWG + threadIdx.x; sl < cnt; sl += gridDim.x * kWG) {
+  for (int64_t sl = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; sl < cnt;
+       sl += static_cast<int64_t>(gridDim.x) * kWG) {
     double nh = 0.0, nl = 0.0, dh = 0.0, dl = 0.0, h = 0.0;
     for (int c = 0; c < C; ++c) {
       const double4 v = fpart[static_cast<int64_t>(sl) * C + c];
@@ -824,7 +825,8 @@ __global__ __launch_bounds__(kWG) void k_bwd_fix2_merge(const int* __restrict__ 
   const int cnt = *count;
   const int C = fix_chunks(cnt, cmax);
   if (C <= 1) return;
-  for (int sl = blockIdx.x * kWG + threadIdx.x; sl < cnt; sl += gridDim.x * kWG) {
+  for (int64_t sl = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; sl < cnt;
+       sl += static_cast<int64_t>(gridDim.x) * kWG) {
     if (slot_hits[sl] > 0) continue;
     double P[2] = {0.0, 0.0}, G[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     for (int c = 0; c < C; ++c) {

@@ -349,8 +349,9 @@ __device__ __forceinline__ double pow_t(double a) {
 }
 
 // Coordinate of padding records in the sweeps' LDS tiles: +inf in FP32 (every weight form
-// gives exactly 0 there), a far finite value in FP64 (weights of about 2^-800 and below,
-// which the one-step forms above handle).
+// gives exactly 0 there), a far finite value in FP64 (the one-step forms above give NaN at
+// +inf).  The forward sweep never visits them (its last tile is cut to the data count); in
+// the data-direction sweeps they carry a zero coefficient, so only their finiteness matters.
 template <typename T>
 __device__ __forceinline__ T padT() {
   return __builtin_huge_valf();
@@ -572,8 +573,11 @@ __device__ __forceinline__ uint8_t route_of(double den, const double* __restrict
 constexpr int kBboxStride = 8;
 
 // Fills the header from the data extent and largest |value|.
-//  s = 2^-e with extent * s in [0.5, 1) for the FP32 sweep (exact scaling that keeps every
-//    weight of points inside the box far from FP32 overflow and underflow), 1 for FP64.
+//  s = 2^-e with extent * s in [0.5, 1), in both precisions: an exact scaling that keeps
+//    every weight of points inside the box far from overflow and underflow (in FP64 it also
+//    keeps the adjoint's w / r2 = d^(-p-2) in range where the caller's units would not, as
+//    at coordinates of 1e-90).  Eq. 1 is invariant under it; the denominators leave the
+//    sweeps in scaled units and are reported in the caller's as D = D_s s^p.
 //  Near-coincidence: a data point closer than 1e-6 of the extent puts the denominator above
 //  (1e-6 * extent)^-p, so queries above it are candidates whose nearest distance is then
 //  checked against 1e-6 * extent (route_of, k_near_check).
@@ -591,13 +595,12 @@ constexpr int kBboxStride = 8;
 __device__ inline void fill_header(double* __restrict__ h, double ext, double vmax, double p,
                                    bool f32s, bool rel) {
   if (!(ext > 0.0) || !(ext < __builtin_huge_val())) ext = 1.0;
-  double s = 1.0;
+  int e = 0;
+  (void)frexp(ext, &e);
+  const double s = ldexp(1.0, -e);
   double cap_s = __DBL_MAX__;
   double lo_s = 0.0;
   if (f32s) {
-    int e = 0;
-    (void)frexp(ext, &e);
-    s = ldexp(1.0, -e);
     cap_s = ldexp(1.0, 80) / fmax(1.0, vmax);
     lo_s = ldexp(1.0, -60);
     if (rel) {

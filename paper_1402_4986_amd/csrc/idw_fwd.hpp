@@ -76,15 +76,20 @@ __device__ __forceinline__ void kahan_add(T& s, T& e, T x) {
 // operations per accumulator and pair; the accuracy variant).
 // REL = true: relative weights, the squared distance multiplied by the query's sigma
 // before the weight is taken (one more multiply per pair).
-template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR, bool KH = false, bool REL = false>
-__device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t jt,
+// TAIL = true: only the first `cnt` records of the tile are data (the chunk's last tile);
+// the padding records after them are never visited, so that no weight of theirs, however
+// small, reaches the denominator.
+template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR, bool KH = false, bool REL = false,
+          bool TAIL = false>
+__device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t jt, int cnt,
                                          const T (&qc)[Q][3], const int64_t (&qi)[Q], T nhp,
                                          const T (&sg)[Q], T (&nh)[Q], T (&nl)[Q], T (&dh)[Q],
                                          T (&dl)[Q]) {
   constexpr int CH = 64;
+  const int lim = TAIL ? cnt : kTile;
   if constexpr (KH) {
 #pragma unroll UNR
-    for (int jj = 0; jj < kTile; ++jj) {
+    for (int jj = 0; jj < lim; ++jj) {
       const P4<T> d = tl[jj];
       const T dv = (DIM == 3) ? d.w : d.z;
 #pragma unroll
@@ -101,15 +106,16 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
     }
     return;
   }
-  for (int c0 = 0; c0 < kTile; c0 += CH) {
+  for (int c0 = 0; c0 < lim; c0 += CH) {
     T an[Q], ad[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       an[k] = T(0);
       ad[k] = T(0);
     }
+    const int ce = TAIL ? ((lim - c0) < CH ? (lim - c0) : CH) : CH;
 #pragma unroll UNR
-    for (int jj = 0; jj < CH; ++jj) {
+    for (int jj = 0; jj < ce; ++jj) {
       const P4<T> d = tl[c0 + jj];
       const T dv = (DIM == 3) ? d.w : d.z;
 #pragma unroll
@@ -225,11 +231,18 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) fetch(t + 1);
     const int64_t jt = jb + static_cast<int64_t>(t) * kTile;
+    const int cnt = static_cast<int>((je - jt) < kTile ? (je - jt) : kTile);
     const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
-    if (diag)
-      fwd_tile<T, DIM, PM, Q, true, 1, KH, REL>(tile[t & 1], jt, qc, qi, nhp, sg, nh, nl, dh, dl);
-    else
-      fwd_tile<T, DIM, PM, Q, false, UNR, KH, REL>(tile[t & 1], jt, qc, qi, nhp, sg, nh, nl, dh, dl);
+    if (cnt < kTile) {
+      if (diag)
+        fwd_tile<T, DIM, PM, Q, true, 1, KH, REL, true>(tile[t & 1], jt, cnt, qc, qi, nhp, sg, nh, nl, dh, dl);
+      else
+        fwd_tile<T, DIM, PM, Q, false, 1, KH, REL, true>(tile[t & 1], jt, cnt, qc, qi, nhp, sg, nh, nl, dh, dl);
+    } else if (diag) {
+      fwd_tile<T, DIM, PM, Q, true, 1, KH, REL>(tile[t & 1], jt, kTile, qc, qi, nhp, sg, nh, nl, dh, dl);
+    } else {
+      fwd_tile<T, DIM, PM, Q, false, UNR, KH, REL>(tile[t & 1], jt, kTile, qc, qi, nhp, sg, nh, nl, dh, dl);
+    }
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }
@@ -299,7 +312,8 @@ __global__ __launch_bounds__(kWG) void k_near_finish(const int* __restrict__ lis
                                                      const double* __restrict__ hdr, uint8_t* __restrict__ route) {
   const int cnt = *count;
   const T near = static_cast<T>(hdr[H_NEAR_R2]);
-  for (int i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; i < cnt;
+       i += static_cast<int64_t>(gridDim.x) * kWG) {
     const int q = list[i];
     route[q] = from_min_bits<T>(minb[q]) < near ? F_FP64 : F_FP32;
   }
@@ -472,7 +486,8 @@ __global__ __launch_bounds__(kWG) void k_fwd_fixmerge(const int* __restrict__ li
   const int cnt = *count;
   const int C = fix_chunks(cnt, cmax);
   if (C <= 1) return;
-  for (int sl = blockIdx.x * kWG + threadIdx.x; sl < cnt; sl += gridDim.x * kWG) {
+  for (int64_t sl = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; sl < cnt;
+       sl += static_cast<int64_t>(gridDim.x) * kWG) {
     double nh = 0.0, nl = 0.0, dh = 0.0, dl = 0.0, hz = 0.0, h = 0.0;
     for (int c = 0; c < C; ++c) {
       const double4 v = fpart[static_cast<int64_t>(sl) * C + c];

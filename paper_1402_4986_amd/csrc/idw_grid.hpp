@@ -154,7 +154,8 @@ __global__ __launch_bounds__(kWG) void k_grid_check(DevPts query, const int* __r
   // Every point whose computed r2 is below nearT differs from q by less than this in each
   // scaled coordinate (the rounding of the subtraction and the sums is far below 1e-4).
   const double rp = sqrt(hdr[H_NEAR_R2]) * 1.0001;
-  for (int i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; i < cnt;
+       i += static_cast<int64_t>(gridDim.x) * kWG) {
     const int64_t q = list[i];
     T c[3] = {T(0), T(0), T(0)};
     Loader<T, DIM, L>::query(query, q, c);
@@ -212,7 +213,8 @@ __global__ __launch_bounds__(kWG) void k_grid_nearest(DevPts query, const double
   // cell near a face (FP64 rounding of (x - bmin) / h), and its FP32 r2 below the exact
   // squared distance by a few ulp.
   const double slack = G.h * 0x1p-28;
-  for (int i = blockIdx.x * kWG + threadIdx.x; i < cnt; i += gridDim.x * kWG) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kWG + threadIdx.x; i < cnt;
+       i += static_cast<int64_t>(gridDim.x) * kWG) {
     const int64_t q = i;
     T c[3] = {T(0), T(0), T(0)};
     Loader<T, DIM, L>::query(query, q, c);

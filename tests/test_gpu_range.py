@@ -116,24 +116,39 @@ def test_batched_large_exponent_and_values():
 
 
 # The FP64 sweeps take a general-p weight as 2^(e nh) from an exponent table times a
-# mantissa table entry and a short series.  The FP64 path does not rescale the coordinates,
-# so factors of 1e-40 and 1e90 put r^2 hundreds of binades away from 1, far into the
-# exponent table; p near 64 stresses the series.  (The adjoint's factor w / r^2 =
-# (r^2)^(-p/2 - 1) must itself stay within the FP64 range: at 1e-90 and p = 2.9 it would
-# reach 1e441.)  The forward, the dz-only adjoint (the data
-# sweep), the dz + dq adjoint (fused, w / r^2 from the tables) and dq alone (the query sweep)
-# run through those weights;
-# few queries may take the FP64 fix-up.
-@pytest.mark.parametrize("scale,p", [(1e-40, 2.9), (1.0, 0.37), (1.0, 17.9), (1.0, 63.5),
+# mantissa table entry and a short series.  Coordinates are scaled by a power of two (the
+# extent into [1/2, 1)) before the sweeps, in FP64 as in FP32, so factors of 1e-90 and 1e90
+# only move the reported denominators by s^p; without that scale, the adjoint's factor
+# w / r^2 = d^(-p-2) would leave the FP64 range at 1e-90 and p = 2.9 (about 1e441), and at
+# 1e-40 the sweeps' r^2 would sit hundreds of binades from 1, far into the exponent table.
+# p near 64 stresses the series.  The forward, the dz-only adjoint (the data sweep), the
+# dz + dq adjoint (fused, w / r^2 from the tables) and dq alone (the query sweep) run
+# through those weights; few queries may take the FP64 fix-up.
+#
+# At 2^-299 (about 1e-90) the oracle itself, which computes in the caller's units, cannot
+# form w / r^2: there the expected values come from the oracle on the unscaled coordinates
+# and the scale law of Eq. 1, exact for a power of two c: Z and dz do not change, D takes
+# the factor c^-p, dq the factor 1/c, and dp does not change (the shift of ln r2 by 2 ln c
+# multiplies sum_j w_ij (z_j - Z_i) = 0).
+@pytest.mark.parametrize("scale,p", [(2.0 ** -299, 2.9), (1e-40, 2.9), (1.0, 0.37), (1.0, 17.9), (1.0, 63.5),
                                      (1e90, 1.3)])
 def test_f64_general_p_across_scales(scale, p):
-    x, z, q = rand_case(71, 3000, 1000, 2, "f64")
-    x, q = x * scale, q * scale
-    q[:4] = x[:4]                                   # exact hits
+    x1, z, q1 = rand_case(71, 3000, 1000, 2, "f64")
+    q1[:4] = x1[:4]                                 # exact hits
+    x, q = x1 * scale, q1 * scale
     g = np.random.default_rng(72).normal(size=len(q))
-    print(f"case scale={scale} p={p}", flush=True)
-    ref = oracle.forward(x, z, q, p)
+    law = scale == 2.0 ** -299
+    print(f"case scale={scale:g} p={p} ({'scale law' if law else 'direct'})", flush=True)
+    if law:
+        ref = oracle.forward(x1, z, q1, p)
+        ref = dict(ref, D=ref["D"] * scale ** -p)
+        gref = oracle.backward(x1, z, q1, p, g)
+        gref = dict(gref, dq=gref["dq"] / scale, dq_cond=gref["dq_cond"] / scale)
+    else:
+        ref = oracle.forward(x, z, q, p)
+        gref = oracle.backward(x, z, q, p, g)
     assert np.all(np.isfinite(ref["Z"])) and np.all(np.isfinite(ref["D"][4:]))
+    assert np.all(np.isfinite(gref["dq"])) and np.all(np.isfinite(gref["dq_cond"]))
     d, qq = points(x, z, q, "aoas", "f64")
     ws = api.workspace(d, qq, "f64")
     Z, D = api.forward(d, qq, p, "f64", ws=ws)
@@ -141,13 +156,14 @@ def test_f64_general_p_across_scales(scale, p):
     nf = int(ws[256:260].view(torch.int32).item())
     assert nf <= 4 + len(q) // 100, f"{nf} queries took the FP64 fix-up"
     assert np.max(scaled_err(Z.cpu().numpy(), ref)) <= TOL["f64"]
+    np.testing.assert_allclose(D.cpu().numpy()[4:], ref["D"][4:], rtol=1e-12)
     dz, _, _ = api.backward(d, qq, p, torch.as_tensor(g, device="cuda"), Z, D, "f64", ws=ws,
                             need_dp=False, need_dq=False)
-    gref = oracle.backward(x, z, q, p, g)
     e = np.abs(dz.cpu().numpy() - gref["dz"]) / gref["dz_scale"]
     assert np.max(e) <= GTOL["f64"], f"dz err {np.max(e):.3e}"
     dz, _, dq = api.backward(d, qq, p, torch.as_tensor(g, device="cuda"), Z, D, "f64", ws=ws,
                              need_dp=False)
+    assert np.all(np.isfinite(dq.cpu().numpy()))
     e = np.abs(dz.cpu().numpy() - gref["dz"]) / gref["dz_scale"]
     assert np.max(e) <= GTOL["f64"], f"dz (with dq) err {np.max(e):.3e}"
     e = np.max(np.abs(dq.cpu().numpy() - gref["dq"])[4:], axis=1) / gref["dq_cond"][4:]
@@ -156,3 +172,36 @@ def test_f64_general_p_across_scales(scale, p):
                             need_dz=False, need_dp=False)    # the query sweep alone
     e = np.max(np.abs(dq.cpu().numpy() - gref["dq"])[4:], axis=1) / gref["dq_cond"][4:]
     assert np.max(e) <= GTOL["f64"], f"dq (alone) err {np.max(e):.3e}"
+    _, dp, _ = api.backward(d, qq, p, torch.as_tensor(g, device="cuda"), Z, D, "f64", ws=ws,
+                            need_dz=False, need_dq=False)    # dp: the log2 / exp2 route
+    assert abs(float(dp) - gref["dp"]) <= GTOL["f64"] * gref["dp_cond"], (float(dp), gref["dp"])
+
+
+# Small exponents: every weight is close to 1 whatever the distance, so a record that is not
+# data but reaches the denominator (the padding after the last data point of a tile) would
+# move Z by about its weight over n.  At p = 0.05 and n = 8 the padding of one tile would
+# add about 6e-5 relative to D.  Coordinates of about 1e118 place the data beyond 2^390:
+# only the power-of-two scale keeps it apart from any far padding coordinate.
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("n", [8, 1000])
+@pytest.mark.parametrize("p", [0.05, 0.1])
+@pytest.mark.parametrize("scale", [1.0, 1e118])
+def test_small_exponent_few_points_and_far_coordinates(prec, n, p, scale):
+    if prec == "f32" and scale != 1.0:
+        pytest.skip("1e118 is beyond the FP32 range")
+    x, z, q = rand_case(80 + n, n, 300, 2, prec)
+    x, q = x * scale, q * scale
+    q[:2] = x[:2]                                   # exact hits
+    print(f"case prec={prec} n={n} p={p} scale={scale:g}", flush=True)
+    ref = oracle.forward(x, z, q, p)
+    assert np.all(np.isfinite(ref["Z"])) and np.all(np.isfinite(ref["D"][2:]))
+    for layout in ("aoas", "soa"):
+        Z, D = gpu_forward(x, z, q, p, layout, prec)
+        assert np.max(scaled_err(Z, ref)) <= TOL[prec]
+        np.testing.assert_allclose(D[2:], ref["D"][2:], rtol=10 * TOL[prec])
+        assert np.array_equal(Z[:2], ref["Z"][:2].astype(np.float32 if prec == "f32" else np.float64))
+    g = np.random.default_rng(81).normal(size=len(q))
+    if prec == "f32":
+        g = g.astype(np.float32).astype(np.float64)
+    gref = oracle.backward(x, z, q, p, g)
+    _check_grad(_backward(x, z, q, p, "hybrid", prec, g), gref, prec, g, p)

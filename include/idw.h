@@ -111,8 +111,10 @@ typedef struct idw_points {
  *   split             number of data chunks swept by separate workgroups and merged in a
  *                     fixed order (1..1024); 0 = chosen from m so the chip is filled
  *   batch_chunk       batched plans: data points per work item (rounded up to 512;
- *                     default 16384)
- *   batch_workgroups  batched plans: persistent workgroups (default 2 per compute unit)
+ *                     default: the autotuned value compiled into the library, see
+ *                     idw_batched_defaults)
+ *   batch_workgroups  batched plans: persistent workgroups (default: the autotuned value,
+ *                     or 2 per compute unit when the library was built without a table)
  *   separate_adjoint  idw_backward: 1 = run the query-direction and data-direction sweeps
  *                     separately instead of the fused sweep (same results within the
  *                     stated tolerances; for comparison).  These sweeps use the direct
@@ -240,6 +242,17 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
 
 /* Device workspace bytes needed by idw_batched for this plan. */
 int idw_batched_plan_workspace(const idw_plan* plan, size_t* bytes);
+
+/* The launch parameters a plan uses: `chunk` = data points per work item (a multiple of
+ * 512), `workgroups` = persistent workgroups asked for (the launch takes at most one per
+ * work item).  Host only; IDW_EINVAL on a null argument. */
+int idw_batched_plan_params(const idw_plan* plan, int64_t* chunk, int32_t* workgroups);
+
+/* The defaults a plan takes where its configuration leaves batch_chunk or batch_workgroups
+ * at 0: the parameters the autotuner chose for gfx950 (a table in the source tree), compiled
+ * into the library by its build.  `workgroups` = 0 stands for two per compute unit.  Host
+ * only, no device needed; IDW_EINVAL on a null argument. */
+int idw_batched_defaults(int64_t* chunk, int32_t* workgroups);
 
 /* Runs every instance of the plan: one graph launch on `stream`. */
 int idw_batched(idw_plan* plan, void* workspace, size_t workspace_bytes, void* stream);

@@ -20,7 +20,8 @@ PRECISION_CODES = {"f32": FP32, "f64": FP64, "f32_kahan": FP32_KAHAN}
 
 EXPORTED = ("idw_version", "idw_last_error", "idw_record_bytes", "idw_workspace_size",
             "idw_forward", "idw_backward", "idw_timing_enable", "idw_timing_read", "idw_batched_plan_create",
-            "idw_batched_plan_workspace", "idw_batched", "idw_batched_plan_destroy")
+            "idw_batched_plan_workspace", "idw_batched", "idw_batched_plan_destroy", "idw_batched_plan_params",
+            "idw_batched_defaults")
 T_FWD_SWEEP, T_BWD_QUERY, T_BWD_DATA, T_BWD_FUSED = 0, 1, 2, 3
 
 
@@ -91,6 +92,10 @@ def load(path: str | None = None):
         lib.idw_batched.argtypes = [vp, vp, sz, vp]
         lib.idw_batched_plan_destroy.restype = None
         lib.idw_batched_plan_destroy.argtypes = [vp]
+        lib.idw_batched_plan_params.restype = ctypes.c_int
+        lib.idw_batched_plan_params.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int32)]
+        lib.idw_batched_defaults.restype = ctypes.c_int
+        lib.idw_batched_defaults.argtypes = [P(ctypes.c_int64), P(ctypes.c_int32)]
         if path is None:
             _lib = lib
         return lib

@@ -2,8 +2,9 @@
 
 Grid-searches the data points per work item (batch_chunk) and the number of persistent
 workgroups (batch_workgroups) on a seeded batched workload, timing graph replays with
-HIP events, and writes the best pair (plus the whole table) to tuning/gfx950.json, which
-BatchedPlan reads by default.
+HIP events, and writes the best pair (plus the whole table) to tuning/gfx950.json.  The
+library's build compiles that pair in as the defaults of every batched plan (a plan whose
+configuration leaves the fields at 0); rebuild after tuning.
 
 Usage: python -m paper_1402_4986_amd.autotune [--count 64] [--out path] [--reps 3]
 """

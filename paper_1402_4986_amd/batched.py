@@ -7,7 +7,6 @@ and queries ({x, y, (z), pad}); each has its own dim, p and sizes.
 from __future__ import annotations
 
 import ctypes
-import json
 import os
 from typing import List, Optional
 
@@ -19,16 +18,6 @@ from ._lib import IdwConfig, IdwInstance, check
 TUNING_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning", "gfx950.json")
 
 
-def load_tuning(path: Optional[str] = None) -> dict:
-    """Tuned batched-plan parameters written by ``paper_1402_4986_amd.autotune``."""
-    p = path or os.environ.get("IDW_TUNE_FILE") or TUNING_FILE
-    try:
-        with open(p) as f:
-            return json.load(f)
-    except (OSError, ValueError):
-        return {}
-
-
 class BatchedPlan:
     """Owns an idw_plan and its workspace; call run() to enqueue all instances.
 
@@ -38,8 +27,9 @@ class BatchedPlan:
 
     def __init__(self, instances: List[dict], chunk: int = 0, workgroups: int = 0, tuning: Optional[dict] = None):
         lib = _lib.load()
-        if tuning is None:
-            tuning = load_tuning()
+        # chunk / workgroups left at 0 take the library's defaults: the autotuned values its
+        # build compiled in (idw_batched_defaults); `tuning` overrides them from a table.
+        tuning = tuning or {}
         chunk = chunk or int(tuning.get("batch_chunk", 0))
         workgroups = workgroups or int(tuning.get("batch_workgroups", 0))
         self._keep = instances
@@ -68,6 +58,12 @@ class BatchedPlan:
         dev = instances[0]["data"].device
         self.workspace = torch.empty(max(need.value, 256), dtype=torch.uint8, device=dev)
         self.device = dev
+
+    def params(self) -> tuple:
+        """(data points per work item, persistent workgroups) of this plan."""
+        c, w = ctypes.c_int64(), ctypes.c_int32()
+        check(_lib.load().idw_batched_plan_params(self._plan, ctypes.byref(c), ctypes.byref(w)))
+        return c.value, w.value
 
     def run(self, stream: Optional[torch.cuda.Stream] = None) -> None:
         lib = _lib.load()

@@ -6,6 +6,7 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
+import json
 import os
 import shutil
 import subprocess
@@ -31,6 +32,25 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+TUNING = os.path.join(HERE, "tuning", f"{ARCH}.json")
+
+
+def tuned_defines(path: str = TUNING) -> list:
+    """The autotuned batched-plan parameters (written by paper_1402_4986_amd.autotune) as
+    compile-time defaults of the library; none when the table is absent."""
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return []
+    out = []
+    for key, macro in (("batch_chunk", "IDW_TUNED_BATCH_CHUNK"), ("batch_workgroups", "IDW_TUNED_BATCH_WORKGROUPS")):
+        v = int(t.get(key, 0))
+        if v > 0:
+            out.append(f"-D{macro}={v}")
+    return out
+
+
 def _units():
     units = []
     for name, idx in LAYOUTS:
@@ -39,6 +59,8 @@ def _units():
     for src in ("idw_common.hip", "idw_batched.hip", "idw_api.cpp"):
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         extra = ["-x", "hip"] if src.endswith(".cpp") else []
+        if src == "idw_batched.hip":
+            extra = extra + tuned_defines()
         units.append((os.path.join(CSRC, src), obj, extra))
     return units
 

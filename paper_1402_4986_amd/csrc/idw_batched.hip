@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kWG) void kb_fixup(const BInst* __restrict__ inst, 
   __shared__ double red[kWG];
   __shared__ long long redi[kWG];
   const int c = *cnt;
-  for (int sl = blockIdx.x; sl < c; sl += gridDim.x) {
+  for (int64_t sl = blockIdx.x; sl < c; sl += gridDim.x) {
     const int64_t g = list[sl];
     const int i = find_inst(inst, count, g);
     const BInst I = inst[i];
@@ -482,6 +482,8 @@ struct idw_plan {
   int64_t mtot = 0;
   int64_t part_elems = 0;  // double2 partial slots
   int grid = 0;            // persistent workgroups
+  int grid_req = 0;        // workgroups asked for (configuration or tuned default), before the
+                           // clamp to the number of work items
   int chunk_target = 0;
   int nrel_items = 0;      // work items of the relative-weight instances (nearest pass)
   std::vector<BInst> host_inst;
@@ -500,7 +502,35 @@ struct idw_plan {
 
 static size_t al256b(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
+// Defaults of the persistent launch when the configuration leaves them at 0: the values the
+// autotuner chose for this architecture, compiled in from its table by the build (item
+// length in data points, persistent workgroups; 0 workgroups stands for two per compute
+// unit).  Without a table: 16,384-point items, two workgroups per compute unit.
+#ifndef IDW_TUNED_BATCH_CHUNK
+#define IDW_TUNED_BATCH_CHUNK 16384
+#endif
+#ifndef IDW_TUNED_BATCH_WORKGROUPS
+#define IDW_TUNED_BATCH_WORKGROUPS 0
+#endif
+static_assert(IDW_TUNED_BATCH_CHUNK > 0 && IDW_TUNED_BATCH_WORKGROUPS >= 0, "tuned batched defaults");
+
 extern "C" {
+
+int idw_batched_defaults(int64_t* chunk, int32_t* workgroups) {
+  clear_error();
+  if (!chunk || !workgroups) return fail(IDW_EINVAL, "null argument");
+  *chunk = (IDW_TUNED_BATCH_CHUNK + kTile - 1) / kTile * kTile;
+  *workgroups = IDW_TUNED_BATCH_WORKGROUPS;
+  return IDW_OK;
+}
+
+int idw_batched_plan_params(const idw_plan* plan, int64_t* chunk, int32_t* workgroups) {
+  clear_error();
+  if (!plan || !chunk || !workgroups) return fail(IDW_EINVAL, "null argument");
+  *chunk = plan->chunk_target;
+  *workgroups = plan->grid_req;
+  return IDW_OK;
+}
 
 int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_t precision,
                             const idw_config* cfg, idw_plan** out_plan) {
@@ -510,9 +540,9 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
   if (!instances || count <= 0) return fail(IDW_EINVAL, "at least one instance is required");
   if (precision != IDW_FP32) return fail(IDW_EUNSUPPORTED, "batched plans run the FP32 sweep only");
   if (const int rc0 = validate_config(cfg)) return rc0;
-  const int chunk_target =
-      (cfg && cfg->batch_chunk > 0) ? static_cast<int>((cfg->batch_chunk + kTile - 1) / kTile * kTile) : 16384;
-  const int grid_req = (cfg && cfg->batch_workgroups > 0) ? cfg->batch_workgroups : 0;
+  const int chunk_req = (cfg && cfg->batch_chunk > 0) ? cfg->batch_chunk : IDW_TUNED_BATCH_CHUNK;
+  const int chunk_target = static_cast<int>((static_cast<int64_t>(chunk_req) + kTile - 1) / kTile * kTile);
+  const int grid_req = (cfg && cfg->batch_workgroups > 0) ? cfg->batch_workgroups : IDW_TUNED_BATCH_WORKGROUPS;
   std::vector<BInst> hi(count);
   int64_t qoff = 0, poff = 0;
   struct Cand {
@@ -582,7 +612,8 @@ int idw_batched_plan_create(const idw_instance* instances, int32_t count, int32_
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  P->grid = grid_req > 0 ? grid_req : cus * 2;
+  P->grid_req = grid_req > 0 ? grid_req : cus * 2;
+  P->grid = P->grid_req;
   if (P->grid > P->nitems && P->nitems > 0) P->grid = P->nitems;
   if (hipMalloc(&P->d_inst, sizeof(BInst) * count) != hipSuccess ||
       hipMalloc(&P->d_items, sizeof(BItem) * std::max<size_t>(1, items.size())) != hipSuccess ||

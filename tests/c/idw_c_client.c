@@ -8,12 +8,15 @@
  *   then n*dim doubles x, n doubles z, m*dim doubles q, m doubles g.
  * Output file: m doubles Z, m doubles D, n doubles dz, 1 double dp, m*dim doubles dq.
  * The sweep runs in FP32 on the hybrid layout (packed coordinates + value array).
+ * With the single argument --batched-params it instead builds a batched plan with no
+ * configuration and prints the launch parameters the plan took.
  * Exit status 0 on success; otherwise the library's error text goes to stderr.
  */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include "../../include/idw.h"
 
@@ -46,9 +49,38 @@ static void* upload(const void* host, size_t bytes) {
   return d;
 }
 
+/* `--batched-params`: builds a batched plan for one small instance with no configuration
+ * and prints the launch parameters it took (the library's compiled-in tuned defaults). */
+static int batched_params(void) {
+  const int64_t n = 1024, m = 256;
+  float* rec = (float*)calloc((size_t)(n + m) * 4, sizeof(float));
+  for (int64_t j = 0; j < n + m; ++j) {
+    rec[4 * j] = (float)(j % 37) / 37.0f;
+    rec[4 * j + 1] = (float)(j % 53) / 53.0f;
+    rec[4 * j + 2] = 1.0f;
+  }
+  void* d = upload(rec, sizeof(float) * 4 * (size_t)n);
+  void* q = upload(rec + 4 * n, sizeof(float) * 4 * (size_t)m);
+  void* z = NULL;
+  CHECK_HIP(hipMalloc(&z, sizeof(float) * m));
+  if (!d || !q) return 2;
+  idw_instance inst = {{{d, NULL, NULL, NULL}, n, 2, IDW_AOAS}, {{q, NULL, NULL, NULL}, m, 2, IDW_AOAS}, 2.0, z, NULL};
+  idw_plan* plan = NULL;
+  CHECK_IDW(idw_batched_plan_create(&inst, 1, IDW_FP32, NULL, &plan));
+  int64_t chunk = 0, dchunk = 0;
+  int32_t wg = 0, dwg = 0;
+  CHECK_IDW(idw_batched_plan_params(plan, &chunk, &wg));
+  CHECK_IDW(idw_batched_defaults(&dchunk, &dwg));
+  idw_batched_plan_destroy(plan);
+  printf("plan chunk=%lld workgroups=%d defaults chunk=%lld workgroups=%d\n", (long long)chunk, wg,
+         (long long)dchunk, dwg);
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc == 2 && strcmp(argv[1], "--batched-params") == 0) return batched_params();
   if (argc != 3) {
-    fprintf(stderr, "usage: %s input.bin output.bin\n", argv[0]);
+    fprintf(stderr, "usage: %s input.bin output.bin | --batched-params\n", argv[0]);
     return 1;
   }
   FILE* f = fopen(argv[1], "rb");

@@ -29,6 +29,16 @@ def test_every_declared_function_is_exported(lib):
     assert lib.idw_version().decode().startswith("idw-gfx950")
 
 
+def test_batched_defaults_are_the_tuning_table(lib):
+    # The build compiles the autotuner's chosen parameters in as the batched plans' defaults.
+    tune = json.load(open(os.path.join(ROOT, "paper_1402_4986_amd", "tuning", "gfx950.json")))
+    c, w = ctypes.c_int64(), ctypes.c_int32()
+    assert lib.idw_batched_defaults(ctypes.byref(c), ctypes.byref(w)) == 0
+    assert (c.value, w.value) == (tune["batch_chunk"], tune["batch_workgroups"])
+    assert lib.idw_batched_defaults(None, ctypes.byref(w)) == _lib.IDW_EINVAL
+    assert lib.idw_batched_plan_params(None, ctypes.byref(c), ctypes.byref(w)) == _lib.IDW_EINVAL
+
+
 def _rb(lib, layout, dim, prec, is_data):
     b = (ctypes.c_size_t * 4)()
     rc = lib.idw_record_bytes(layout, dim, prec, is_data, b)

@@ -4,7 +4,9 @@ from a file.  On the CPU the client must compile and link warning-free; on the G
 results are checked against the FP64 oracle (forward 1e-5 of the condition scale, the
 gradients at their FP32 tolerances, exact hits bit-exact)."""
 import importlib.util
+import json
 import os
+import re
 import subprocess
 
 import numpy as np
@@ -63,3 +65,19 @@ def test_c_client_matches_oracle(tmp_path):
     assert np.max(np.abs(dz - rb["dz"]) / rb["dz_scale"]) <= 1e-5
     assert abs(dp - rb["dp"]) <= 1e-5 * rb["dp_cond"]
     assert np.max(np.max(np.abs(dq - rb["dq"]), axis=1) / np.maximum(rb["dq_cond"], 1e-300)) <= 1e-5
+
+
+@pytest.mark.gpu
+def test_c_client_batched_plan_takes_the_tuned_defaults():
+    # A plan made from plain C with no configuration runs with the autotuned item length and
+    # persistent workgroup count of the tuning table, compiled into the library.
+    exe = c_client.EXE
+    assert os.path.exists(exe), "build the C client first (__graft_entry__.build())"
+    tune = json.load(open(os.path.join(os.path.dirname(HERE), "paper_1402_4986_amd", "tuning", "gfx950.json")))
+    print("c client --batched-params", flush=True)
+    res = subprocess.run([exe, "--batched-params"], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
+                         timeout=120)
+    assert res.returncode == 0, res.stdout
+    got = re.search(r"plan chunk=(\d+) workgroups=(\d+)", res.stdout)
+    assert got, res.stdout
+    assert (int(got.group(1)), int(got.group(2))) == (tune["batch_chunk"], tune["batch_workgroups"])

@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "query×data pairs/sec, IDW fwd+bwd at 1M×1M FP32; % FP32 VALU peak; err vs FP64"
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector: 256 CU x 2.4 GHz x 256 FLOP/clk/CU
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector
 
 # Algorithmic FLOP per query x data pair, 2-D, p = 2 (add/sub/mul = 1, fma = 2,
 # transcendental = 1; compensation and bookkeeping not counted):
@@ -35,6 +36,26 @@ FLOP_PER_PAIR = {"fwd_sweep": 9, "bwd_query": 16, "bwd_data": 8, "bwd_fused": 18
 # per coordinate = 23; the separate data sweep computing dz and dx is 2 sub, mul + fma, rcp,
 # mul (a w), add (dz), mul (f), sub + mul (z - Z), 2 fma = 15.
 FLOP_PER_PAIR_DX = {"bwd_data": 15, "bwd_fused": 23}
+
+
+def fwd_flop_per_pair(dim: int, p: float) -> int:
+    """Algorithmic FLOP per pair of the forward sweep by weight class (same convention):
+    r^2 is dim sub, mul and dim - 1 fma; the weight is rcp (p = 2), rsq (p = 1), rsq and two
+    mul (p = 3), rsq, mul, sqrt and mul (p = 2.5), or log2, mul and exp2 (general p); the
+    accumulation is fma (num) and add (den)."""
+    r2 = dim + 1 + 2 * (dim - 1)
+    w = {1.0: 1, 2.0: 1, 3.0: 3, 2.5: 4}.get(float(p), 3)
+    return r2 + w + 3
+
+
+def adjoint_flop_per_pair(dim: int, p: float) -> int:
+    """Algorithmic FLOP per pair of the fused adjoint (dz, dp, dq) at general p: r^2, log2,
+    mul and exp2 (w / r^2), mul (w = (w / r^2) r^2), sub (z - Z), mul (t = w c), fma (P),
+    mul (u = (w / r^2) c), dim fma (G), fma (dz).  At p = 2 it is FLOP_PER_PAIR["bwd_fused"]."""
+    if float(p) == 2.0 and dim == 2:
+        return FLOP_PER_PAIR["bwd_fused"]
+    r2 = dim + 1 + 2 * (dim - 1)
+    return r2 + 3 + 1 + 1 + 1 + 2 + 1 + 2 * dim + 2
 
 
 def kernel_source_hash() -> str:
@@ -121,6 +142,153 @@ def cpu_baseline_all_cores(x, z, q, g, per_proc: int):
                       f"(dz, dp, dq), FP64, {nproc} processes, {dt:.1f} s wall"}
 
 
+def _events_ms(fn, reps: int) -> float:
+    """Mean duration of fn() over `reps` calls, bracketed by events on the current stream
+    (one untimed call first)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _sweep_ms(lib, fn, reps: int) -> float:
+    """Mean duration of the forward sweep kernel over `reps` calls of fn (library events)."""
+    import ctypes
+
+    import torch
+
+    from paper_1402_4986_amd import _lib
+    fn()
+    torch.cuda.synchronize()
+    _lib.check(lib.idw_timing_enable(1))
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    _lib.check(lib.idw_timing_read(_lib.T_FWD_SWEEP, ctypes.byref(ms), ctypes.byref(cnt)))
+    _lib.check(lib.idw_timing_enable(0))
+    return ms.value / max(cnt.value, 1)
+
+
+def _rate(pairs: float, ms: float, flop: float) -> dict:
+    tf = flop * pairs / (ms * 1e-3) / 1e12
+    return {"ms": round(ms, 3), "pairs_per_s": pairs / (ms * 1e-3), "tflops": round(tf, 2),
+            "frac_of_peak": round(tf / PEAK_FP32_TFLOPS, 4)}
+
+
+def other_configs(lib, dev) -> dict:
+    """Throughput of the other workloads: 10K x 10K FP64 (p = 2), the 3-D mixture (262,144 x
+    1,048,576, p = 2.5: FP32, FP32-Kahan and FP64 forward), the gradient workload (131,072^2,
+    p = 1.5: forward + adjoint step, and the leave-one-out fit of p), and the 64-instance
+    batched graph.  frac_of_peak is against the FP32 vector peak for every entry (the FP64
+    ones are also given against the FP64 peak)."""
+    import numpy as np
+    import torch
+
+    from paper_1402_4986_amd import api, batched, workloads
+    res = {}
+
+    def pts(x, z, q, layout, prec):
+        d = api.Points.from_arrays(workloads.pack_data(x, z, layout, prec), len(x), x.shape[1], layout, dev)
+        qq = api.Points.from_arrays(workloads.pack_query(q, layout, prec), len(q), q.shape[1], layout, dev)
+        return d, qq
+
+    # 10,240 x 10,240, 2-D, FP64, p = 2
+    c = workloads.WORKLOADS["plain2d_f64_10k"]
+    x, z, q, _ = workloads.plain2d(c["n"], c["m"], "f64", cfg=c["cfg"])
+    d, qq = pts(x, z, q, "aoas", "f64")
+    ws = api.workspace(d, qq, "f64")
+    Z64 = torch.empty(len(q), dtype=torch.float64, device=dev)
+    D64 = torch.empty(len(q), dtype=torch.float64, device=dev)
+    fwd = lambda: api.forward(d, qq, 2.0, "f64", out_z=Z64, out_den=D64, ws=ws)
+    r = _rate(float(c["n"]) * c["m"], _events_ms(fwd, 10), fwd_flop_per_pair(2, 2.0))
+    r["frac_of_fp64_peak"] = round(r["tflops"] / PEAK_FP64_TFLOPS, 4)
+    res["plain2d_f64_10k"] = {"forward_f64": r, "note": "whole idw_forward call; 1.05e8 pairs"}
+    del d, qq, ws, Z64, D64
+
+    # 3-D mixture, p = 2.5
+    c = workloads.WORKLOADS["mixture3d_p2.5_262k_1m"]
+    x, z, q, _ = workloads.mixture3d(c["n"], c["m"], c["hits"], "f32", cfg=c["cfg"])
+    pairs = float(c["n"]) * c["m"]
+    fl = fwd_flop_per_pair(3, 2.5)
+    entry = {"flop_per_pair": fl}
+    for prec in ("f32", "f32_kahan", "f64"):
+        d, qq = pts(x, z, q, "aoas", prec)
+        ws = api.workspace(d, qq, prec)
+        t = torch.float64 if prec == "f64" else torch.float32
+        Zo = torch.empty(len(q), dtype=t, device=dev)
+        Do = torch.empty(len(q), dtype=torch.float64, device=dev)
+        fwd = lambda: api.forward(d, qq, 2.5, prec, out_z=Zo, out_den=Do, ws=ws)
+        call = _rate(pairs, _events_ms(fwd, 3), fl)
+        sweep = _rate(pairs, _sweep_ms(lib, fwd, 3), fl)
+        if prec == "f64":
+            call["frac_of_fp64_peak"] = round(call["tflops"] / PEAK_FP64_TFLOPS, 4)
+            sweep["frac_of_fp64_peak"] = round(sweep["tflops"] / PEAK_FP64_TFLOPS, 4)
+        entry[prec] = {"call": call, "sweep": sweep}
+        del d, qq, ws, Zo, Do
+    res["mixture3d_p2.5_262k_1m"] = entry
+
+    # gradient workload: one forward + adjoint (dz, dp, dq) step, and the leave-one-out fit
+    c = workloads.WORKLOADS["plain2d_grad_f32_128k"]
+    x, z, q, tgt = workloads.plain2d(c["n"], c["m"], "f32", cfg=c["cfg"])
+    pg = c["p"]
+    d, qq = pts(x, z, q, "hybrid", "f32")
+    ws = api.workspace(d, qq, "f32")
+    Zg = torch.empty(len(q), dtype=torch.float32, device=dev)
+    Dg = torch.empty(len(q), dtype=torch.float64, device=dev)
+    tt = torch.tensor(tgt, dtype=torch.float32, device=dev)
+    g = torch.empty(len(q), dtype=torch.float32, device=dev)
+
+    def gstep():
+        api.forward(d, qq, pg, "f32", out_z=Zg, out_den=Dg, ws=ws)
+        torch.sub(Zg, tt, out=g).mul_(2.0 / len(q))
+        api.backward(d, qq, pg, g, Zg, Dg, "f32", ws=ws)
+
+    pairs = float(c["n"]) * c["m"]
+    ms = _events_ms(gstep, 5)
+    fl = fwd_flop_per_pair(2, pg) + adjoint_flop_per_pair(2, pg)
+    step = _rate(pairs, ms, fl)
+    step["flop_per_pair"] = fl
+    X = torch.tensor(x, dtype=torch.float32, device=dev)
+    zt = torch.tensor(z, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p_fit, hist = api.fit_p_loo(X, zt, p0=pg, steps=50)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
+    res["plain2d_grad_f32_128k"] = {"step_fwd_bwd": step, "loo_fit": {
+        "seconds": round(fit_s, 3), "evaluations": len(hist), "p0": pg, "p_fit": round(p_fit, 5),
+        "loss0": hist[0][1], "loss_fit": min(h[1] for h in hist),
+        "note": "L-BFGS on the leave-one-out loss of all 131,072 points, at most 50 evaluations"}}
+    del d, qq, ws, X, zt
+
+    # 64 batched instances, one graph launch
+    insts_np = workloads.batched(count=64, cfg=4)
+    insts, bpairs, bflop = [], 0.0, 0.0
+    for i in insts_np:
+        insts.append(dict(data=torch.tensor(workloads.pack_data(i["x"], i["z"], "aoas", "f32")[0], device=dev),
+                          query=torch.tensor(workloads.pack_query(i["q"], "aoas", "f32")[0], device=dev),
+                          dim=i["dim"], p=i["p"], out_z=torch.empty(len(i["q"]), dtype=torch.float32, device=dev)))
+        pr = float(len(i["x"])) * len(i["q"])
+        bpairs += pr
+        bflop += pr * fwd_flop_per_pair(i["dim"], i["p"])
+    plan = batched.BatchedPlan(insts)
+    ms = _events_ms(plan.run, 5)
+    chunk, wg = plan.params()
+    plan.close()
+    r = _rate(bpairs, ms, bflop / bpairs)
+    r.update({"pairs": bpairs, "flop_per_pair_mean": round(bflop / bpairs, 3), "batch_chunk": chunk,
+              "batch_workgroups": wg})
+    res["batched_x64"] = {"graph_launch": r}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +303,8 @@ def main():
                     help="run the adjoint as separate query- and data-direction sweeps")
     ap.add_argument("--need-dx", action="store_true",
                     help="also compute the gradient with respect to the data coordinates")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the timings of the other workloads (10K FP64, 3-D mixture, gradient, batched)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one device-to-device copy of 512 MiB (counter calibration)")
     args = ap.parse_args()
@@ -309,15 +479,24 @@ def main():
         api.forward(data, query, p, "f32", out_z=Z, out_den=D, ws=ws)
         torch.cuda.synchronize()
 
+    if not args.no_configs:
+        out["configs"] = other_configs(lib, dev)
+        api.forward(data, query, p, "f32", out_z=Z, out_den=D, ws=ws)
+        torch.cuda.synchronize()
+
     if not args.no_cpu:
         Zh = Z.cpu().numpy().astype(np.float64)
         rec, idx, ref = cpu_baseline(x, z, q, g, args.cpu_sample, Zh)
         out["cpu_baseline"] = rec
         out["cpu_baseline_all_cores"] = all_cores
         err = np.abs(Zh[idx] - ref["Z"]) / ref["S"]
+        keep = np.abs(ref["Z"]) >= 0.1 * np.max(np.abs(z))
+        plain = np.abs(Zh[idx][keep] - ref["Z"][keep]) / np.abs(ref["Z"][keep])
         out["err_vs_fp64"] = {"max": float(err.max()), "median": float(np.median(err)),
                               "metric": "|Z - Z_oracle| / (sum w|z| / sum w)",
-                              "sample": int(len(idx))}
+                              "plain_rel_max": float(plain.max()), "plain_rel_median": float(np.median(plain)),
+                              "plain_rel_metric": "|Z - Z_oracle| / |Z_oracle| where |Z_oracle| >= 0.1 max|z|",
+                              "plain_rel_count": int(keep.sum()), "sample": int(len(idx))}
     print(json.dumps(out), flush=True)
 
 

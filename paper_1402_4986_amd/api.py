@@ -10,6 +10,7 @@ import ctypes
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -218,17 +219,46 @@ def loo_loss(X: torch.Tensor, z: torch.Tensor, p: torch.Tensor) -> torch.Tensor:
 
 
 def fit_p_loo(X: torch.Tensor, z: torch.Tensor, p0: float = 1.5, steps: int = 50, lr: float = 0.05,
-              clamp=(0.05, 6.0)):
-    """Fits p by Adam on the leave-one-out loss; returns (p, history of (p, loss))."""
-    p = torch.tensor(float(p0), dtype=torch.float64, device=X.device, requires_grad=True)
-    opt = torch.optim.Adam([p], lr=lr)
+              clamp=(0.05, 6.0), method: str = "lbfgs"):
+    """Fits p to the leave-one-out loss; returns (p, history of (p, loss) per evaluation).
+
+    method "lbfgs" (default): L-BFGS with a strong-Wolfe line search over u, where
+      p = lo + (hi - lo) sigmoid(u) keeps every trial p inside `clamp`; `steps` bounds the
+      evaluations of the loss and its gradient.  On a smooth one-dimensional loss it reaches
+      the minimiser in a few evaluations.
+    method "adam": `steps` Adam steps of rate `lr` on p, clamped after each step.
+    """
+    lo, hi = float(clamp[0]), float(clamp[1])
     hist = []
-    for _ in range(steps):
+    if method == "adam":
+        p = torch.tensor(float(p0), dtype=torch.float64, device=X.device, requires_grad=True)
+        opt = torch.optim.Adam([p], lr=lr)
+        for _ in range(steps):
+            opt.zero_grad()
+            loss = loo_loss(X, z, p)
+            loss.backward()
+            hist.append((float(p.detach()), float(loss.detach())))
+            opt.step()
+            with torch.no_grad():
+                p.clamp_(lo, hi)
+        return float(p.detach()), hist
+    if method != "lbfgs":
+        raise ValueError(f"unknown method {method!r}")
+    if not lo < float(p0) < hi:
+        raise ValueError("p0 must lie strictly inside clamp")
+    t = (float(p0) - lo) / (hi - lo)
+    u = torch.tensor(float(np.log(t / (1.0 - t))), dtype=torch.float64, device=X.device, requires_grad=True)
+    opt = torch.optim.LBFGS([u], lr=1.0, max_iter=steps, max_eval=steps, history_size=10,
+                            tolerance_grad=1e-12, tolerance_change=1e-12, line_search_fn="strong_wolfe")
+    p_of = lambda v: lo + (hi - lo) * torch.sigmoid(v)
+
+    def closure():
         opt.zero_grad()
+        p = p_of(u)
         loss = loo_loss(X, z, p)
         loss.backward()
         hist.append((float(p.detach()), float(loss.detach())))
-        opt.step()
-        with torch.no_grad():
-            p.clamp_(clamp[0], clamp[1])
-    return float(p.detach()), hist
+        return loss
+
+    opt.step(closure)
+    return float(p_of(u.detach())), hist

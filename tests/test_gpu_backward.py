@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import GTOL, TOL, points, rand_case
+from gpu_helpers import GTOL, TOL, dp_errors, dq_errors, points, rand_case
 from paper_1402_4986_amd import api
 
 pytestmark = pytest.mark.gpu
@@ -40,10 +40,13 @@ def _check(got, ref, prec):
         e = np.abs(dz - ref["dz"]) / np.maximum(ref["dz_scale"], 1e-300)
         assert np.max(e) <= tol, f"dz err {np.max(e):.3e}"
     if dp is not None:
-        assert abs(dp - ref["dp"]) <= tol * ref["dp_cond"], f"dp {dp} vs {ref['dp']}"
+        ec, es = dp_errors(dp, ref)
+        assert ec <= tol and es <= tol, f"dp {dp} vs {ref['dp']}"
     if dq is not None:
-        e = np.max(np.abs(dq - ref["dq"]), axis=1) / np.maximum(ref["dq_cond"], 1e-300)
-        assert np.max(e) <= tol, f"dq err {np.max(e):.3e}"
+        ec, es = dq_errors(dq, ref)
+        assert np.max(ec) <= tol, f"dq err {np.max(ec):.3e}"
+        # well-conditioned rows are held to their own (centred) absolute-term sum as well
+        assert es.size == 0 or np.max(es) <= tol, f"dq err (centred scale) {np.max(es):.3e}"
 
 
 @pytest.mark.parametrize("layout", ["hybrid", "aoas", "soa"])
@@ -124,11 +127,15 @@ def test_loo_fit_reduces_the_loss():
     x, z, _ = rand_case(27, 4096, 1, 2, "f32")
     X = torch.tensor(x, dtype=torch.float32, device="cuda")
     zt = torch.tensor(z, dtype=torch.float32, device="cuda")
-    p, hist = api.fit_p_loo(X, zt, p0=1.5, steps=20, lr=0.1)
-    assert hist[-1][1] < hist[0][1]
-    # the loss at the fitted p agrees with the oracle's leave-one-out loss
-    assert oracle.loo_loss(x, z, p) == pytest.approx(float(api.loo_loss(X, zt, torch.tensor(p, device="cuda"))),
-                                                     rel=1e-4)
+    for method in ("adam", "lbfgs"):
+        p, hist = api.fit_p_loo(X, zt, p0=1.5, steps=20, lr=0.1, method=method)
+        assert hist[-1][1] < hist[0][1] and len(hist) <= 20
+        # the loss at the fitted p agrees with the oracle's leave-one-out loss, within what
+        # the forward's tolerance (1e-5 S per query) allows: mean(2 e |Z - z| + e^2)
+        r = oracle.forward(x, z, x, p, self_index=np.arange(len(x)))
+        e = 1e-5 * r["S"]
+        got = float(api.loo_loss(X, zt, torch.tensor(p, dtype=torch.float64, device="cuda")))
+        assert abs(got - np.mean((r["Z"] - z) ** 2)) <= np.mean(2 * e * np.abs(r["Z"] - z) + e * e)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -170,24 +177,28 @@ def test_fused_and_separate_adjoint_sweeps(separate, dim, p):
     _check(got, oracle.backward(x, z, q, p, g), "f32")
 
 
-def test_fused_adjoint_accumulates_over_query_blocks():
-    # 1,000,000 data points in 16 ranges and 100,000 queries (98 blocks of 1,024): the 64
-    # workgroup groups of the fused sweep each fold one or two query blocks into their dz
-    # row.  The upstream gradient is non-zero on 150 scattered queries only, so the oracle
-    # needs just those queries for the exact dz, dp and dq.
-    x, z, q = rand_case(32, 1000000, 100000, 2)
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_fused_adjoint_accumulates_over_query_blocks(prec):
+    # 1,000,000 data points in 16 ranges and 100,000 queries: in FP32, 98 blocks of 1,024
+    # queries on 64 workgroup groups; in FP64, 196 blocks of 512 on 128 groups.  Each group
+    # folds one or two query blocks into its dz row.  The upstream gradient is non-zero on
+    # 150 scattered queries only, so the oracle needs just those queries for the exact dz,
+    # dp and dq.
+    t = np.float32 if prec == "f32" else np.float64
+    x, z, q = rand_case(32, 1000000, 100000, 2, prec)
     r = np.random.default_rng(33)
     sel = np.sort(r.choice(len(q), size=150, replace=False))
     g = np.zeros(len(q))
-    g[sel] = r.normal(size=150).astype(np.float32)
-    d, qq = points(x, z, q, "soa", "f32")
-    Z, D = api.forward(d, qq, 2.0, "f32")
-    gt = torch.tensor(g, dtype=torch.float32, device="cuda")
-    dz, dp, dq = api.backward(d, qq, 2.0, gt, Z, D, "f32")
+    g[sel] = r.normal(size=150).astype(t)
+    print(f"fused fold prec={prec}", flush=True)
+    d, qq = points(x, z, q, "soa", prec)
+    Z, D = api.forward(d, qq, 2.0, prec)
+    gt = torch.tensor(g, dtype=torch.float32 if prec == "f32" else torch.float64, device="cuda")
+    dz, dp, dq = api.backward(d, qq, 2.0, gt, Z, D, prec)
     torch.cuda.synchronize()
     ref = oracle.backward(x, z, q[sel], 2.0, g[sel])
     dqh = dq.cpu().numpy().astype(np.float64)
     got = (dz.cpu().numpy().astype(np.float64), float(dp), dqh[sel])
-    _check(got, ref, "f32")
+    _check(got, ref, prec)
     rest = np.setdiff1d(np.arange(len(q)), sel)
     assert np.all(dqh[rest] == 0.0)

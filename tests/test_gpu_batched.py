@@ -92,7 +92,7 @@ def test_full_batched_workload_sampled():
     worst = 0.0
     for src, inst in zip(insts_np, insts):
         got = inst["out_z"].cpu().numpy().astype(np.float64)
-        idx = rng.choice(len(src["q"]), size=min(24, len(src["q"])), replace=False)
+        idx = rng.choice(len(src["q"]), size=min(64, len(src["q"])), replace=False)
         ref = oracle.forward(src["x"], src["z"], src["q"][idx], src["p"])
         worst = max(worst, float(np.max(scaled_err(got[idx], ref))))
         assert np.all(np.isfinite(got))

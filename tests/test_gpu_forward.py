@@ -9,7 +9,8 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import TOL, gpu_forward, points, rand_case, scaled_err
+from gpu_helpers import (GTOL, PLAIN_TOL, TOL, dp_errors, dq_errors, gpu_forward, oracle_backward_par,
+                         oracle_forward_par, plain_rel_err, points, rand_case, scaled_err)
 from paper_1402_4986_amd import api, workloads
 
 pytestmark = pytest.mark.gpu
@@ -151,19 +152,60 @@ def _sample(m, k, seed):
     return np.sort(np.random.default_rng(seed).choice(m, size=k, replace=False))
 
 
-@pytest.mark.parametrize("layout", ["soa", "aos", "aoas"])
-def test_full_size_plain2d_1m_sampled(layout):
-    # The benchmark's workload (1,048,576 x 1,048,576, FP32, p = 2) in the benchmark's
-    # launch configuration; the oracle evaluates 192 sampled queries one by one.
+@pytest.fixture(scope="module")
+def plain2d_1m():
+    # The benchmark's workload (1,048,576 x 1,048,576, 2-D, p = 2) and the oracle on 4,096
+    # queries sampled by seed, evaluated one by one (in parallel over query slices).
     cfg = workloads.WORKLOADS["plain2d_f32_1m"]
     x, z, q, _ = workloads.plain2d(cfg["n"], cfg["m"], "f32", cfg=cfg["cfg"])
-    print(f"full-size plain2d layout={layout}", flush=True)
-    Z, D = gpu_forward(x, z, q, 2.0, layout, "f32")
-    idx = _sample(len(q), 192, 1)
-    ref = oracle.forward(x, z, q[idx], 2.0)
-    assert np.max(scaled_err(Z[idx], ref)) <= TOL["f32"]
-    np.testing.assert_allclose(D[idx], ref["D"], rtol=1e-5)
+    idx = _sample(len(q), 4096, 1)
+    return x, z, q, idx, oracle_forward_par(x, z, q[idx], 2.0)
+
+
+@pytest.mark.parametrize("prec,layout", [("f32", l) for l in LAYOUTS] + [("f64", "aoas")])
+def test_full_size_plain2d_1m_sampled(prec, layout, plain2d_1m):
+    # FP32 in every record layout and FP64 (whose forward finishes in the sweep kernel at
+    # this size: one data chunk), in the launch configuration of the benchmark.  Both error
+    # measures: relative to the summation scale on every sampled query, and plain relative
+    # error where |Z| >= 0.1 max|z|.
+    x, z, q, idx, ref = plain2d_1m
+    print(f"full-size plain2d prec={prec} layout={layout}", flush=True)
+    Z, D = gpu_forward(x, z, q, 2.0, layout, prec)
+    assert np.max(scaled_err(Z[idx], ref)) <= TOL[prec]
+    pr = plain_rel_err(Z[idx], ref, z)
+    assert pr.size > 1000 and np.max(pr) <= PLAIN_TOL[prec], f"plain relative error {np.max(pr):.3e}"
+    np.testing.assert_allclose(D[idx], ref["D"], rtol=1e-5 if prec == "f32" else 1e-12)
     assert np.all(np.isfinite(Z))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_full_size_plain2d_1m_adjoint_sparse_upstream(prec, plain2d_1m):
+    # The full-size adjoint (dz, dp, dq) in the benchmark's launch configuration, with the
+    # upstream gradient non-zero on the 4,096 sampled queries only: dz and dp are then sums
+    # over those queries alone, which the oracle evaluates exactly.  Every workgroup group of
+    # the fused sweep folds 16 query blocks into its dz row at this size.
+    x, z, q, idx, _ = plain2d_1m
+    t = np.float32 if prec == "f32" else np.float64
+    g = np.zeros(len(q))
+    g[idx] = np.random.default_rng(2).normal(size=len(idx)).astype(t)
+    d, qq = points(x, z, q, "aoas", prec)
+    print(f"full-size plain2d adjoint prec={prec}", flush=True)
+    Z, D = api.forward(d, qq, 2.0, prec)
+    gt = torch.tensor(g, dtype=torch.float32 if prec == "f32" else torch.float64, device="cuda")
+    dz, dp, dq = api.backward(d, qq, 2.0, gt, Z, D, prec)
+    torch.cuda.synchronize()
+    ref = oracle_backward_par(x, z, q[idx], 2.0, g[idx])
+    tol = GTOL[prec]
+    dzh = dz.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(dzh - ref["dz"]) / ref["dz_scale"]) <= tol
+    ec, es = dp_errors(float(dp), ref)
+    assert ec <= tol and es <= tol
+    dqh = dq.cpu().numpy().astype(np.float64)
+    ec, es = dq_errors(dqh[idx], ref)
+    assert np.max(ec) <= tol, f"dq err {np.max(ec):.3e}"
+    assert es.size > 100 and np.max(es) <= tol, f"dq err (centred scale) {np.max(es):.3e}"
+    rest = np.setdiff1d(np.arange(len(q)), idx)
+    assert np.all(dqh[rest] == 0.0)
 
 
 def test_full_size_mixture3d_hits_and_fp32_vs_fp64():
@@ -177,10 +219,13 @@ def test_full_size_mixture3d_hits_and_fp32_vs_fp64():
     assert np.all(ref_h["H"] >= 1)
     np.testing.assert_array_equal(Z32[hit_rows], ref_h["Z"].astype(np.float32).astype(np.float64))
     np.testing.assert_array_equal(Z64[hit_rows], ref_h["Z"])
-    idx = _sample(len(q), 128, 2)
-    ref = oracle.forward(x, z, q[idx], 2.5)
+    idx = _sample(len(q), 4096, 2)
+    ref = oracle_forward_par(x, z, q[idx], 2.5)
     assert np.max(scaled_err(Z32[idx], ref)) <= TOL["f32"]
     assert np.max(scaled_err(Z64[idx], ref)) <= TOL["f64"]
+    for Zp, prec in ((Z32, "f32"), (Z64, "f64")):
+        pr = plain_rel_err(Zp[idx], ref, z)
+        assert pr.size > 1000 and np.max(pr) <= PLAIN_TOL[prec], f"{prec} plain relative error {np.max(pr):.3e}"
     # FP32 path against the GPU FP64 path for every query
     rel = np.abs(Z32 - Z64) / np.maximum(np.abs(Z64), 1e-3)
     assert np.max(rel) <= 1e-5
@@ -199,6 +244,8 @@ def test_full_size_plain2d_f64_10k_every_query(layout, plain2d_10k):
     x, z, q, ref = plain2d_10k
     Z, D = gpu_forward(x, z, q, 2.0, layout, "f64")
     assert np.max(scaled_err(Z, ref)) <= TOL["f64"]
+    pr = plain_rel_err(Z, ref, z)
+    assert pr.size > 2000 and np.max(pr) <= PLAIN_TOL["f64"]
     np.testing.assert_allclose(D, ref["D"], rtol=1e-12)
 
 

@@ -180,6 +180,22 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
                 uint32_t flags, void* out_z, double* out_den, void* workspace,
                 size_t workspace_bytes, void* stream, const idw_config* cfg);
 
+/* idw_forward for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation and
+ * results, bit for bit, with the workspace taken from a static device array of the library
+ * (64 MiB per device, held from the first call on that device until the process ends)
+ * instead of a caller buffer.  The caller still passes the point sets and out_z / out_den
+ * as for idw_forward.  Sizes whose forward workspace (idw_workspace_size with no IDW_NEED_*
+ * bit) exceeds 64 MiB are rejected with IDW_EWORKSPACE before anything is enqueued; the
+ * benchmark size n = m = 2^20 fits in both precisions.  Allocates nothing and calls no
+ * allocating routine.  Every call on a device uses that device's one array, and leaves
+ * its contents behind: calls that overlap on one device (other streams, other threads, or
+ * a second call before the first has completed on a different stream) race and give
+ * undefined results; calls in order on one stream do not.  (With kernel timing switched on
+ * by idw_timing_enable, its sweep records HIP events as idw_forward's does.) */
+int idw_forward_noalloc(const idw_points* data, const idw_points* query, double p, int32_t precision,
+                        uint32_t flags, void* out_z, double* out_den, void* stream, const idw_config* cfg);
+
 /* Adjoint of idw_forward: given grad_out[i] = dL/dZ_i, writes
  *   grad_z [n]       dL/dz_j   (element type of precision)   if flags & IDW_NEED_DZ
  *   grad_p [1]       dL/dp     (double, device)              if flags & IDW_NEED_DP

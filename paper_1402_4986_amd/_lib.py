@@ -21,7 +21,7 @@ PRECISION_CODES = {"f32": FP32, "f64": FP64, "f32_kahan": FP32_KAHAN}
 EXPORTED = ("idw_version", "idw_last_error", "idw_record_bytes", "idw_workspace_size",
             "idw_forward", "idw_backward", "idw_timing_enable", "idw_timing_read", "idw_batched_plan_create",
             "idw_batched_plan_workspace", "idw_batched", "idw_batched_plan_destroy", "idw_batched_plan_params",
-            "idw_batched_defaults")
+            "idw_batched_defaults", "idw_forward_noalloc")
 T_FWD_SWEEP, T_BWD_QUERY, T_BWD_DATA, T_BWD_FUSED = 0, 1, 2, 3
 
 
@@ -76,6 +76,9 @@ def load(path: str | None = None):
         lib.idw_forward.restype = ctypes.c_int
         lib.idw_forward.argtypes = [P(IdwPoints), P(IdwPoints), ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
                                     vp, vp, vp, sz, vp, P(IdwConfig)]
+        lib.idw_forward_noalloc.restype = ctypes.c_int
+        lib.idw_forward_noalloc.argtypes = [P(IdwPoints), P(IdwPoints), ctypes.c_double, ctypes.c_int32,
+                                            ctypes.c_uint32, vp, vp, vp, P(IdwConfig)]
         lib.idw_backward.restype = ctypes.c_int
         lib.idw_backward.argtypes = [P(IdwPoints), P(IdwPoints), ctypes.c_double, ctypes.c_int32, ctypes.c_uint32,
                                      vp, vp, vp, vp, vp, vp, vp, vp, sz, vp, P(IdwConfig)]

@@ -285,6 +285,30 @@ DevPts dev_pts(const idw_points* P) {
   return d;
 }
 
+// ---- static scratch of idw_forward_noalloc ----
+// The forward's workspace for callers that cannot allocate: one array per device, held by
+// the loaded code object until the process ends.  Host code never passes `scratch` itself
+// (on the host it is only a stand-in for the device symbol): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static int scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {nullptr};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(IDW_EDEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(IDW_EDEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+    addr[dev] = ptr;
+  }
+  *out = addr[dev];
+  return IDW_OK;
+}
+
 int check_workspace(void* ws, size_t bytes, size_t need) {
   if (!ws) return fail(IDW_EWORKSPACE, "workspace is null");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(IDW_EWORKSPACE, "workspace must be 256-byte aligned");
@@ -509,10 +533,11 @@ int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t 
   return IDW_OK;
 }
 
-int idw_forward(const idw_points* data, const idw_points* query, double p, int32_t precision,
-                uint32_t flags, void* out_z, double* out_den, void* workspace,
-                size_t workspace_bytes, void* stream, const idw_config* cfg) {
-  clear_error();
+// The forward's checks and launches on a caller workspace (idw_forward) or on the
+// library's static scratch (idw_forward_noalloc).
+static int forward_impl(const idw_points* data, const idw_points* query, double p, int32_t precision,
+                        uint32_t flags, void* out_z, double* out_den, void* workspace,
+                        size_t workspace_bytes, void* stream, const idw_config* cfg, bool static_scratch) {
   int rc = validate_common(data, query, p, precision, flags);
   if (rc) return rc;
   if ((rc = validate_config(cfg))) return rc;
@@ -527,6 +552,15 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
   if (m == 0) return IDW_OK;
   if (!out_z) return fail(IDW_EINVAL, "out_z is null");
   const WsPlan w = plan_workspace(data, query, precision, cfg);
+  if (static_scratch) {
+    if (w.fwd_total > kScratchBytes)
+      return fail(IDW_EWORKSPACE, "idw_forward_noalloc: these sizes need %zu bytes of scratch, above its %zu",
+                  w.fwd_total, kScratchBytes);
+    rc = check_device();
+    if (rc) return rc;
+    if ((rc = scratch_address(&workspace))) return rc;
+    workspace_bytes = kScratchBytes;
+  }
   rc = check_workspace(workspace, workspace_bytes, w.fwd_total);
   if (rc) return rc;
   rc = check_device();
@@ -575,6 +609,20 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
     return rc;
   if ((rc = check_hip(F.fwd_fixup(a, f64, st), "FP64 fix-up"))) return rc;
   return IDW_OK;
+}
+
+int idw_forward(const idw_points* data, const idw_points* query, double p, int32_t precision,
+                uint32_t flags, void* out_z, double* out_den, void* workspace,
+                size_t workspace_bytes, void* stream, const idw_config* cfg) {
+  clear_error();
+  return forward_impl(data, query, p, precision, flags, out_z, out_den, workspace, workspace_bytes, stream, cfg,
+                      false);
+}
+
+int idw_forward_noalloc(const idw_points* data, const idw_points* query, double p, int32_t precision,
+                        uint32_t flags, void* out_z, double* out_den, void* stream, const idw_config* cfg) {
+  clear_error();
+  return forward_impl(data, query, p, precision, flags, out_z, out_den, nullptr, 0, stream, cfg, true);
 }
 
 int idw_backward(const idw_points* data, const idw_points* query, double p, int32_t precision,

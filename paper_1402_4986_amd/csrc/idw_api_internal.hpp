@@ -34,6 +34,11 @@ struct WsPlan {
   size_t grid_cnt = 0, grid_start = 0, grid_bsum = 0, grid_rec = 0, grid_blist = 0;
 };
 
+// Static device scratch of idw_forward_noalloc (the forward's workspace for callers that
+// cannot allocate): 64 MiB, enough for the forward at n = m = 2^20 in FP32 (37 MB) and FP64
+// (54 MB).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+
 int fail(int code, const char* fmt, ...);
 void clear_error();
 int check_hip(hipError_t e, const char* what);

@@ -125,6 +125,30 @@ def test_bad_arguments_are_rejected_on_the_host(lib, case, code):
     assert lib.idw_last_error().decode() != ""
 
 
+def test_noalloc_forward_checks_its_scratch_limit_on_the_host(lib):
+    # idw_forward_noalloc takes its workspace from a 64 MiB static device array: sizes whose
+    # forward workspace exceeds it are refused before anything touches the device, as are
+    # the arguments idw_forward refuses.
+    def call(d, q, p=2.0, prec=_lib.FP32):
+        return lib.idw_forward_noalloc(ctypes.byref(d), ctypes.byref(q), p, prec, 0, 0x8000000, None, None, None)
+    b = ctypes.c_size_t()
+    big_d, big_q = _pts(1 << 22, 2, _lib.AOAS), _pts(1 << 22, 2, _lib.AOAS, base=0x20000000)
+    assert lib.idw_workspace_size(ctypes.byref(big_d), ctypes.byref(big_q), _lib.FP32, 0, None, ctypes.byref(b)) == 0
+    assert b.value > 64 << 20
+    assert call(big_d, big_q) == _lib.IDW_EWORKSPACE
+    assert "scratch" in lib.idw_last_error().decode()
+    d, q = _pts(1000, 2, _lib.AOAS), _pts(500, 2, _lib.AOAS, base=0x20000000)
+    assert call(d, q, p=0.0) == _lib.IDW_EINVAL
+    assert call(d, q, prec=7) == _lib.IDW_EINVAL
+    q0 = _pts(0, 2, _lib.AOAS)
+    assert call(d, q0) == 0                          # no queries: a no-op, as idw_forward
+    # the benchmark size fits the scratch in both precisions
+    for prec in (_lib.FP32, _lib.FP64):
+        s = _pts(1 << 20, 2, _lib.AOAS)
+        assert lib.idw_workspace_size(ctypes.byref(s), ctypes.byref(s), prec, 0, None, ctypes.byref(b)) == 0
+        assert b.value <= 64 << 20
+
+
 def test_zero_queries_is_a_no_op(lib):
     d = _pts(1000, 3, _lib.SOA)
     q = _pts(0, 3, _lib.SOA)

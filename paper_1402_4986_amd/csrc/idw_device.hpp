@@ -383,8 +383,11 @@ __device__ __forceinline__ double weight_sweep(double r2, double nhp) {
     const double t = rcp64_w(r2);
     return t * t;
   } else if constexpr (PM == PM_25) {
+    // d^-2.5 = s^3 / sqrt(s) with s = d^-1: two one-step reciprocal square roots and three
+    // multiplies, where s^2 sqrt(s) would pay for the library's correctly rounded square
+    // root (about a dozen instructions with its scaling and special cases)
     const double s = rsq64_w(r2);
-    return s * s * sqrt(s);
+    return s * s * s * rsq64_w(s);
   } else {  // general p: the tables of pow_t (pow_table_init in the calling kernel)
     return pow_t(r2);
   }

@@ -64,9 +64,12 @@ def test_max_data_count_forward_and_adjoint(p):
     torch.cuda.empty_cache()
 
 
-def test_max_query_count_forward():
-    n, m = 64, NMAX
-    print(f"n={n} m={m} FP32 aoas", flush=True)
+@pytest.mark.parametrize("n,p", [(64, 2.0), (65536, 8.0)])
+def test_max_query_count_forward(n, p):
+    # p = 8 with 65,536 data points runs the relative weights with the grid's ring search
+    # for every query's nearest distance: its grid-stride loops reach index 2^31 - 2.
+    m = NMAX
+    print(f"n={n} m={m} FP32 aoas p={p}", flush=True)
     rng = np.random.default_rng(910)
     x = rng.random((n, 2)).astype(np.float32)
     z = np.full(n, 0.7, dtype=np.float32)
@@ -81,13 +84,13 @@ def test_max_query_count_forward():
     query[0, :2] = data[9, :2]                        # and at the first
     d = api.Points([data], n, 2, "aoas")
     q = api.Points([query], m, 2, "aoas")
-    Z, D = api.forward(d, q, 2.0, "f32")
+    Z, D = api.forward(d, q, p, "f32")
     torch.cuda.synchronize()
     assert float(Z[m - 1]) == np.float32(1.3) and float(Z[0]) == np.float32(0.7)
     assert float(Z.min()) >= np.float32(0.7) - 1e-6 and float(Z.max()) <= np.float32(1.3) + 1e-6
     idx = np.unique(np.concatenate([rng.integers(0, m, size=4096), [1, m // 2, m - 2]]))
     qs = query[torch.tensor(idx, device="cuda"), :2].double().cpu().numpy()
-    ref = oracle.forward(x.astype(np.float64), z.astype(np.float64), qs, 2.0)
+    ref = oracle.forward(x.astype(np.float64), z.astype(np.float64), qs, p)
     got = Z[torch.tensor(idx, device="cuda")].double().cpu().numpy()
     assert np.max(scaled_err(got, ref)) <= TOL["f32"]
     del data, query, Z, D

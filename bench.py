@@ -257,6 +257,7 @@ def other_configs(lib, dev) -> dict:
     step["flop_per_pair"] = fl
     X = torch.tensor(x, dtype=torch.float32, device=dev)
     zt = torch.tensor(z, dtype=torch.float32, device=dev)
+    api.fit_p_loo(X, zt, p0=pg, steps=3)  # untimed: the optimiser's first-call set-up in torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     p_fit, hist = api.fit_p_loo(X, zt, p0=pg, steps=50)

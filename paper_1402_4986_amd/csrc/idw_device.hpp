@@ -211,10 +211,16 @@ __device__ __forceinline__ double rsq64_w(double a) {
 //    whose reciprocal (rounded) and -log2 of that rounded reciprocal the table holds;
 //    r = m (1/c_k) - 1 has |r| <= 2^-9 (one rounding, in the fma), and log2(m) =
 //    -log2(1/c_k) + log2(1 + r), the latter as r times the series of ln(1 + r) / ln 2
-//    through r^7 (truncation below 2^-63 relative).  The exponent is added last, so the
-//    result is accurate relative to itself.  About 18 instructions against about 33 for
-//    log2_64.  Zero and subnormal a give -inf (such pairs are exact or near-coincident
-//    hits, which go to the FP64 fix-up); +inf and NaN are not expected (finite padding).
+//    through r^5: the first term left out, r^6 / (6 ln 2), is below 1.3e-17, under the
+//    rounding of any result but those within 2^-6 of 0 (a within 1% of 1), where the
+//    absolute error stays near 1e-17.  The sweeps need absolute accuracy: the power
+//    gradient's terms are held relative to sum w |ln r2| (|z| + |Z|), and a general-p weight
+//    2^(nh log2 r2) moves by |nh| ln2 times the error, below 3e-16 for p <= 64.  The
+//    exponent is added last.  About 13 instructions against about 33 for log2_64.  Only
+//    normal positive a are meaningful: a zero or subnormal a (an exact or near-coincident
+//    hit) gives an unspecified finite value; the sweeps never keep a result computed from
+//    one (such queries are recomputed by the FP64 fix-up, and the data-direction sweeps move
+//    them to a far coordinate).  +inf and NaN are not expected (finite padding).
 //  exp2_t: k = round(256 x), x = k/256 + f with |f| <= 1/512 (exact); 2^x = 2^(k >> 8)
 //    2^((k & 255)/256) 2^f, the table holding 2^(j/256) (rounded) and 2^f its Taylor series
 //    in f ln 2 through the fifth power (truncation below 2^-54); v_ldexp applies 2^(k >> 8),
@@ -256,15 +262,12 @@ __device__ __forceinline__ double log2_t(double a) {
   const double m = __builtin_bit_cast(double, (b & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
   const double2 t = log2_table()[k];
   const double r = fma(m, t.x, -1.0);
-  double p = L / 7.0;
-  p = fma(p, r, -L / 6.0);
-  p = fma(p, r, L / 5.0);
+  double p = L / 5.0;
   p = fma(p, r, -L / 4.0);
   p = fma(p, r, L / 3.0);
   p = fma(p, r, -L / 2.0);
   p = fma(p, r, L);
-  const double res = fma(r, p, t.y) + e;
-  return a >= 0x1p-1022 ? res : -__builtin_huge_val();
+  return fma(r, p, t.y) + e;
 }
 
 __device__ __forceinline__ double exp2_t(double x) {

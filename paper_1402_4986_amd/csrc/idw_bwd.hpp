@@ -132,6 +132,11 @@ __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt,
                                           T (&gh)[Q][3], T (&gl)[Q][3]) {
   constexpr int CH = 64;
   const int lim = TAIL ? cnt : kTile;
+  // One 64-record block at a time, merged before the next: unrolled over the tile, the
+  // compiler keeps every block's sums live to the tile's end (FP32 p = 2 with dp and dq:
+  // 127 VGPRs against 78; FP64: 249 against 148).  Measured at 1M x 1M, block by block is
+  // 2% faster for dq alone in FP32 and 3% for the FP64 query + data sweeps.
+#pragma unroll 1
   for (int c0 = 0; c0 < lim; c0 += CH) {
     T ap[Q], ag[Q][3];
 #pragma unroll
@@ -560,6 +565,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
     const bool diag = excl && it < x0 + kWG * Q && x0 < it + kTile;
     const P4<T>* tl = tile[t & 1];
     const T* zt = ztl[t & 1];
+    // block by block, as the query sweep (the dz + dx sweep: 219 VGPRs against 110 in FP32,
+    // 4-5% faster at 1M x 1M in both precisions)
+#pragma unroll 1
     for (int c0 = 0; c0 < kTile; c0 += 64) {
       T az[Q], ax[Q][3];
 #pragma unroll

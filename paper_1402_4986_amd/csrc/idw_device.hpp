@@ -207,8 +207,9 @@ __device__ __forceinline__ double rsq64_w(double a) {
 // 2^(-p/2 log2 r2)), from two 256-entry tables in LDS.  Every lane indexes them with its
 // own value; 16-entry tables (conflict-free, but two and four more polynomial terms)
 // measured 10-15% slower at 1M x 1M.
-//  log2_t: a = 2^e m with m in [1, 2); the top 8 mantissa bits k pick c_k = 1 + (k + 1/2)/256,
-//    whose reciprocal (rounded) and -log2 of that rounded reciprocal the table holds;
+//  log2_t: a = 2^e m with m in [1/2, 1) (v_frexp_mant / v_frexp_exp); the top 8 mantissa
+//    bits k pick c_k = (1 + (k + 1/2)/256) / 2, whose reciprocal (rounded) and -log2 of that
+//    rounded reciprocal the table holds;
 //    r = m (1/c_k) - 1 has |r| <= 2^-9 (one rounding, in the fma), and log2(m) =
 //    -log2(1/c_k) + log2(1 + r), the latter as r times the series of ln(1 + r) / ln 2
 //    through r^5: the first term left out, r^6 / (6 ln 2), is below 1.3e-17, under the
@@ -216,11 +217,11 @@ __device__ __forceinline__ double rsq64_w(double a) {
 //    absolute error stays near 1e-17.  The sweeps need absolute accuracy: the power
 //    gradient's terms are held relative to sum w |ln r2| (|z| + |Z|), and a general-p weight
 //    2^(nh log2 r2) moves by |nh| ln2 times the error, below 3e-16 for p <= 64.  The
-//    exponent is added last.  About 13 instructions against about 33 for log2_64.  Only
-//    normal positive a are meaningful: a zero or subnormal a (an exact or near-coincident
-//    hit) gives an unspecified finite value; the sweeps never keep a result computed from
-//    one (such queries are recomputed by the FP64 fix-up, and the data-direction sweeps move
-//    them to a far coordinate).  +inf and NaN are not expected (finite padding).
+//    exponent is added last.  About 11 instructions against about 33 for log2_64.  Positive
+//    finite a, subnormals included, are meaningful; a = 0 (an exact hit) gives an unspecified
+//    finite value, and the sweeps never keep a result computed from one (such queries are
+//    recomputed by the FP64 fix-up, and the data-direction sweeps move them to a far
+//    coordinate).  +inf and NaN are not expected (finite padding).
 //  exp2_t: k = round(256 x), x = k/256 + f with |f| <= 1/512 (exact); 2^x = 2^(k >> 8)
 //    2^((k & 255)/256) 2^f, the table holding 2^(j/256) (rounded) and 2^f its Taylor series
 //    in f ln 2 through the fifth power (truncation below 2^-54); v_ldexp applies 2^(k >> 8),
@@ -243,7 +244,7 @@ __device__ __forceinline__ double* exp2_table() {
 __device__ __forceinline__ void log2_table_init() {
   const int t = threadIdx.x;
   if (t < kLogTab) {
-    const double c = 1.0 + (t + 0.5) / kLogTab;
+    const double c = 0.5 * (1.0 + (t + 0.5) / kLogTab);
     const double inv = 1.0 / c;
     log2_table()[t] = make_double2(inv, -log2(inv));
   }
@@ -255,11 +256,10 @@ __device__ __forceinline__ void exp2_table_init() {
 
 __device__ __forceinline__ double log2_t(double a) {
   constexpr double L = 1.44269504088896340736;  // 1 / ln 2
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, a);
-  const unsigned int hi = static_cast<unsigned int>(b >> 32);
+  const double m = __builtin_amdgcn_frexp_mant(a);
+  const double e = static_cast<double>(__builtin_amdgcn_frexp_exp(a));
+  const unsigned int hi = static_cast<unsigned int>(__builtin_bit_cast(unsigned long long, m) >> 32);
   const int k = static_cast<int>((hi >> 12) & (kLogTab - 1));
-  const double e = static_cast<double>(static_cast<int>((hi >> 20) & 0x7ff) - 1023);
-  const double m = __builtin_bit_cast(double, (b & 0x000fffffffffffffull) | 0x3ff0000000000000ull);
   const double2 t = log2_table()[k];
   const double r = fma(m, t.x, -1.0);
   double p = L / 5.0;

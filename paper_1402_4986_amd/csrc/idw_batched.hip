@@ -218,9 +218,12 @@ __device__ __forceinline__ void kb_item(const BInst& I, const BItem& it, const d
     qc[k][1] = r.y * s;
     qc[k][2] = r.z * s;
   }
-  float nh[kBQ], nl[kBQ], dh[kBQ], dl[kBQ];
+  BlockSum<float> nacc[kBQ], dacc[kBQ];
 #pragma unroll
-  for (int k = 0; k < kBQ; ++k) nh[k] = nl[k] = dh[k] = dl[k] = 0.f;
+  for (int k = 0; k < kBQ; ++k) {
+    nacc[k].zero();
+    dacc[k].zero();
+  }
   float4 rr[2];
   auto fetch = [&](int t) {
 #pragma unroll
@@ -266,15 +269,15 @@ __device__ __forceinline__ void kb_item(const BInst& I, const BItem& it, const d
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
     if (t + 1 < ntiles) fetch(t + 1);
-    fwd_tile<float, DIM, PM, kBQ, false, 4, false, REL>(tile[t & 1], 0, kTile, qc, qi, I.nhp, sg, nh, nl, dh, dl);
+    fwd_tile<float, DIM, PM, kBQ, false, 4, false, REL>(tile[t & 1], 0, kTile, qc, qi, I.nhp, sg, nacc, dacc);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < kBQ; ++k) {
     if (qi[k] < I.m) {
-      const double num = (static_cast<double>(nh[k]) + static_cast<double>(nl[k])) * fs[k];
-      const double den = (static_cast<double>(dh[k]) + static_cast<double>(dl[k])) * fs[k];
+      const double num = nacc[k].value() * fs[k];
+      const double den = dacc[k].value() * fs[k];
       part[I.part_off + static_cast<int64_t>(it.chunk) * I.m + qi[k]] = make_double2(num, den);
     }
   }

@@ -9,7 +9,8 @@
 //
 // Three sweeps:
 //  * query sweep: lanes own queries, data tiles broadcast from LDS; accumulates
-//    P_i = sum w (z - Z) log2(r2) and G_i = sum (w/r2)(z - Z)(q - x) with blocked TwoSum;
+//    P_i = sum w (z - Z) log2(r2) and G_i = sum (w/r2)(z - Z)(q - x) over 64-record
+//    blocks added into BlockSum running sums;
 //    writes per-(data chunk, query) partials that a merge kernel turns into dq_i and
 //    per-workgroup dp partials in a fixed order;
 //  * data sweep: lanes own data points, query tiles (q_i, a_i = g_i / D_i) broadcast from
@@ -128,8 +129,8 @@ __device__ __forceinline__ T wr_times(T t, T c, T f) {
 template <typename T, int DIM, int PM, int Q, bool DIAG, bool TAIL, bool NDP, bool NDQ, int UNR>
 __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt, int64_t jt,
                                           const T (&qc)[Q][3], const T (&zq)[Q],
-                                          const int64_t (&qi)[Q], T nhp, T (&ph)[Q], T (&pl)[Q],
-                                          T (&gh)[Q][3], T (&gl)[Q][3]) {
+                                          const int64_t (&qi)[Q], T nhp, BlockSum<T> (&P)[Q],
+                                          BlockSum<T> (&G)[Q][3]) {
   constexpr int CH = 64;
   const int lim = TAIL ? cnt : kTile;
   // One 64-record block at a time, merged before the next: unrolled over the tile, the
@@ -181,10 +182,10 @@ __device__ __forceinline__ void bwdq_tile(const P4<T>* __restrict__ tl, int cnt,
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      if constexpr (NDP) two_sum_acc(ph[k], pl[k], ap[k]);
+      if constexpr (NDP) P[k].add(ap[k]);
       if constexpr (NDQ) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) two_sum_acc(gh[k][d], gl[k][d], ag[k][d]);
+        for (int d = 0; d < DIM; ++d) G[k][d].add(ag[k][d]);
       }
     }
   }
@@ -227,12 +228,12 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 #pragma unroll
     for (int d = 0; d < 3; ++d) qc[k][d] = c[d] * s;
   }
-  T ph[Q], pl[Q], gh[Q][3], gl[Q][3];
+  BlockSum<T> P[Q], G[Q][3];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    ph[k] = pl[k] = T(0);
+    P[k].zero();
 #pragma unroll
-    for (int d = 0; d < 3; ++d) gh[k][d] = gl[k][d] = T(0);
+    for (int d = 0; d < 3; ++d) G[k][d].zero();
   }
 
   T rc[2][3], rv[2];
@@ -266,14 +267,14 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
     const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
     if (cnt < kTile) {
       if (diag)
-        bwdq_tile<T, DIM, PM, Q, true, true, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+        bwdq_tile<T, DIM, PM, Q, true, true, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, P, G);
       else
-        bwdq_tile<T, DIM, PM, Q, false, true, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+        bwdq_tile<T, DIM, PM, Q, false, true, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, P, G);
     } else {
       if (diag)
-        bwdq_tile<T, DIM, PM, Q, true, false, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+        bwdq_tile<T, DIM, PM, Q, true, false, NDP, NDQ, 1>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, P, G);
       else
-        bwdq_tile<T, DIM, PM, Q, false, false, NDP, NDQ, UNR>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, ph, pl, gh, gl);
+        bwdq_tile<T, DIM, PM, Q, false, false, NDP, NDQ, UNR>(tile[t & 1], cnt, jt, qc, zq, qi, nhp, P, G);
     }
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
@@ -282,10 +283,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
   for (int k = 0; k < Q; ++k) {
     if (qi[k] < m) {
       double4 r;
-      r.x = static_cast<double>(ph[k]) + static_cast<double>(pl[k]);
-      r.y = static_cast<double>(gh[k][0]) + static_cast<double>(gl[k][0]);
-      r.z = static_cast<double>(gh[k][1]) + static_cast<double>(gl[k][1]);
-      r.w = static_cast<double>(gh[k][2]) + static_cast<double>(gl[k][2]);
+      r.x = P[k].value();
+      r.y = G[k][0].value();
+      r.z = G[k][1].value();
+      r.w = G[k][2].value();
       part[static_cast<int64_t>(blockIdx.y) * m + qi[k]] = r;
     }
   }
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(kWG) void k_bwd_qmerge(const double4* __restrict__ 
 template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR>
 __device__ __forceinline__ void bwdd_tile(const P4<T>* __restrict__ tl, int64_t it,
                                           const T (&xc)[Q][3], const int64_t (&xj)[Q], T nhp,
-                                          T (&zh)[Q], T (&zl)[Q]) {
+                                          BlockSum<T> (&Zs)[Q]) {
   constexpr int CH = 64;
   for (int c0 = 0; c0 < kTile; c0 += CH) {
     T az[Q];
@@ -365,7 +366,7 @@ __device__ __forceinline__ void bwdd_tile(const P4<T>* __restrict__ tl, int64_t 
       }
     }
 #pragma unroll
-    for (int k = 0; k < Q; ++k) two_sum_acc(zh[k], zl[k], az[k]);
+    for (int k = 0; k < Q; ++k) Zs[k].add(az[k]);
   }
 }
 
@@ -404,9 +405,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 #pragma unroll
     for (int d = 0; d < 3; ++d) xc[k][d] = c[d] * s;
   }
-  T zh[Q], zl[Q];
+  BlockSum<T> Zs[Q];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) zh[k] = zl[k] = T(0);
+  for (int k = 0; k < Q; ++k) Zs[k].zero();
 
   T rc[2][3], ra[2];
   auto fetch = [&](int t) {
@@ -444,17 +445,16 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
     const int64_t it = ib + static_cast<int64_t>(t) * kTile;
     const bool diag = excl && it < x0 + kWG * Q && x0 < it + kTile;
     if (diag)
-      bwdd_tile<T, DIM, PM, Q, true, 1>(tile[t & 1], it, xc, xj, nhp, zh, zl);
+      bwdd_tile<T, DIM, PM, Q, true, 1>(tile[t & 1], it, xc, xj, nhp, Zs);
     else
-      bwdd_tile<T, DIM, PM, Q, false, UNR>(tile[t & 1], it, xc, xj, nhp, zh, zl);
+      bwdd_tile<T, DIM, PM, Q, false, UNR>(tile[t & 1], it, xc, xj, nhp, Zs);
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < Q; ++k)
     if (xj[k] < n)
-      part[static_cast<int64_t>(blockIdx.y) * n + xj[k]] =
-          static_cast<double>(zh[k]) + static_cast<double>(zl[k]);
+      part[static_cast<int64_t>(blockIdx.y) * n + xj[k]] = Zs[k].value();
 }
 
 template <typename T>
@@ -477,8 +477,8 @@ __device__ __forceinline__ T farT() {
 }
 
 // Data sweep with the data-coordinate gradient: lanes own Q data points (scaled coordinates
-// and value), query tiles (q_i, a_i) and Z_i are broadcast from LDS.  Accumulates, with
-// blocked TwoSum as the data sweep,
+// and value), query tiles (q_i, a_i) and Z_i are broadcast from LDS.  Accumulates, over
+// 64-record blocks as the data sweep,
 //   dz_j = sum_i a_i w_ij     and     X_j = sum_i a_i (w_ij / r2_ij)(z_j - Z_i)(q_i - x_j)
 // over query chunk c: part_z[c * n + j] and part_x[(c * n + j) * DIM + e] (double).
 template <typename T, int DIM, int L, int PM, int Q, int UNR = 2>
@@ -512,12 +512,12 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
     for (int d = 0; d < 3; ++d) xc[k][d] = c[d] * s;
     xv[k] = v;
   }
-  T zh[Q], zl[Q], xh[Q][3], xl[Q][3];
+  BlockSum<T> Zs[Q], Xs[Q][3];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    zh[k] = zl[k] = T(0);
+    Zs[k].zero();
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xh[k][d] = xl[k][d] = T(0);
+    for (int d = 0; d < 3; ++d) Xs[k][d].zero();
   }
 
   T rc[2][3], ra[2], rz[2];
@@ -605,9 +605,9 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
       }
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        two_sum_acc(zh[k], zl[k], az[k]);
+        Zs[k].add(az[k]);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) two_sum_acc(xh[k][d], xl[k][d], ax[k][d]);
+        for (int d = 0; d < DIM; ++d) Xs[k][d].add(ax[k][d]);
       }
     }
     if (t + 1 < ntiles) put((t + 1) & 1);
@@ -617,10 +617,10 @@ __global__ __launch_bounds__(kWG) void k_bwd_datax(DevPts data, int64_t n, DevPt
   for (int k = 0; k < Q; ++k) {
     if (xj[k] < n) {
       const int64_t r = static_cast<int64_t>(blockIdx.y) * n + xj[k];
-      part_z[r] = static_cast<double>(zh[k]) + static_cast<double>(zl[k]);
+      part_z[r] = Zs[k].value();
 #pragma unroll
       for (int d = 0; d < DIM; ++d)
-        part_x[r * DIM + d] = static_cast<double>(xh[k][d]) + static_cast<double>(xl[k][d]);
+        part_x[r * DIM + d] = Xs[k][d].value();
     }
   }
 }

@@ -238,12 +238,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
 #pragma unroll
       for (int d = 0; d < 3; ++d) qc[k][d] = ok ? c[d] * s : static_cast<T>(kFarF);
     }
-    T ph[Q], pl[Q], gh[Q][3], gl[Q][3];
+    BlockSum<T> P[Q], G[Q][3];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      ph[k] = pl[k] = T(0);
+      P[k].zero();
 #pragma unroll
-      for (int d = 0; d < 3; ++d) gh[k][d] = gl[k][d] = T(0);
+      for (int d = 0; d < 3; ++d) G[k][d].zero();
     }
 
     fetch(0);
@@ -279,10 +279,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
         }
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-          if constexpr (NDP) two_sum_acc(ph[k], pl[k], ap[k]);
+          if constexpr (NDP) P[k].add(ap[k]);
           if constexpr (NDQ) {
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) two_sum_acc(gh[k][d], gl[k][d], ag[k][d]);
+            for (int d = 0; d < DIM; ++d) G[k][d].add(ag[k][d]);
           }
         }
       }
@@ -315,10 +315,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8))) vo
     for (int k = 0; k < Q; ++k) {
       if (qi[k] < m) {
         double4 r;
-        r.x = static_cast<double>(ph[k]) + static_cast<double>(pl[k]);
-        r.y = static_cast<double>(gh[k][0]) + static_cast<double>(gl[k][0]);
-        r.z = static_cast<double>(gh[k][1]) + static_cast<double>(gl[k][1]);
-        r.w = static_cast<double>(gh[k][2]) + static_cast<double>(gl[k][2]);
+        r.x = P[k].value();
+        r.y = G[k][0].value();
+        r.z = G[k][1].value();
+        r.w = G[k][2].value();
         part_q[static_cast<int64_t>(blockIdx.y) * m + qi[k]] = r;
       }
     }

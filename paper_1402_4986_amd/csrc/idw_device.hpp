@@ -428,6 +428,27 @@ __device__ __forceinline__ void two_sum_acc(T& hi, T& lo, T x) {
   lo += e;
 }
 
+// Running sum of a blocked sweep: the plain sum of each 64-record block is added into it.
+// FP32 block sums go into one FP64 accumulator (a conversion and an FP64 add, 2 VALU
+// operations, where a TwoSum into an FP32 (hi, lo) pair takes 6; the same 2 registers, and
+// the FP64 rounding is finer than the pair's); FP64 block sums keep a TwoSum pair.
+template <typename T>
+struct BlockSum;
+template <>
+struct BlockSum<float> {
+  double s;
+  __device__ __forceinline__ void zero() { s = 0.0; }
+  __device__ __forceinline__ void add(float x) { s += static_cast<double>(x); }
+  __device__ __forceinline__ double value() const { return s; }
+};
+template <>
+struct BlockSum<double> {
+  double hi, lo;
+  __device__ __forceinline__ void zero() { hi = lo = 0.0; }
+  __device__ __forceinline__ void add(double x) { two_sum_acc(hi, lo, x); }
+  __device__ __forceinline__ double value() const { return hi + lo; }
+};
+
 // Neumaier accumulator for the FP64 fix-up paths.
 struct NSum {
   double s = 0.0, c = 0.0;

@@ -5,13 +5,16 @@
 // in flight while tile t is consumed), and every record is broadcast from LDS to all lanes
 // of the wavefront (the shared-memory tiling of Section 4.2, re-derived for wave64).  Each
 // lane accumulates sum w*z and sum w for its queries in plain arithmetic over 64-record
-// blocks and folds every block into (hi, lo) pairs with TwoSum, so the sum error is that of
-// a 64-term sum, not of an n-term one.  The ratio is taken in FP64.  A query whose
+// blocks and adds every block sum into an FP64 running sum (a TwoSum pair in the FP64
+// sweep), so the sum error is that of a 64-term sum, not of an n-term one.  The ratio is
+// taken in FP64.  A query whose
 // denominator exceeds the near-coincidence threshold (or is not finite) is flagged for the
 // FP64 fix-up kernel, which recomputes it exactly, including the exact-hit rule.
 #pragma once
 
 #include <math.h>
+
+#include <type_traits>
 
 #include "idw_device.hpp"
 #include "idw_launch.hpp"
@@ -60,31 +63,35 @@ __device__ __forceinline__ P4<T> stage(const T (&c)[3], T v, T s) {
   return r;
 }
 
-// Kahan step: adds x to the pair (s, e), e carrying the rounding error lost so far
-// (s + e is the compensated sum).
+// Kahan-compensated running sum in the working precision, updated on every pair: s carries
+// the sum and e the rounding error lost so far (s + e is the compensated sum).
 template <typename T>
-__device__ __forceinline__ void kahan_add(T& s, T& e, T x) {
-  const T y = x + e;
-  const T t = s + y;
-  e = y - (t - s);
-  s = t;
-}
+struct KahanSum {
+  T s, e;
+  __device__ __forceinline__ void zero() { s = e = T(0); }
+  __device__ __forceinline__ void add(T x) {
+    const T y = x + e;
+    const T t = s + y;
+    e = y - (t - s);
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return static_cast<double>(s) + static_cast<double>(e); }
+};
 
 // Consume one LDS tile: for each of the lane's Q queries, accumulate w*z and w.
-// KH = false: plain sums over 64-record blocks, each merged into (hi, lo) by TwoSum.
-// KH = true: Kahan-compensated update of (hi, lo) on every pair (about 3 more VALU
-// operations per accumulator and pair; the accuracy variant).
+// KH = false: plain sums over 64-record blocks, each added into a BlockSum.
+// KH = true: a Kahan step on every pair into a KahanSum (about 3 more VALU operations per
+// accumulator and pair; the accuracy variant).
 // REL = true: relative weights, the squared distance multiplied by the query's sigma
 // before the weight is taken (one more multiply per pair).
 // TAIL = true: only the first `cnt` records of the tile are data (the chunk's last tile);
 // the padding records after them are never visited, so that no weight of theirs, however
 // small, reaches the denominator.
 template <typename T, int DIM, int PM, int Q, bool DIAG, int UNR, bool KH = false, bool REL = false,
-          bool TAIL = false>
+          bool TAIL = false, typename Acc>
 __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t jt, int cnt,
                                          const T (&qc)[Q][3], const int64_t (&qi)[Q], T nhp,
-                                         const T (&sg)[Q], T (&nh)[Q], T (&nl)[Q], T (&dh)[Q],
-                                         T (&dl)[Q]) {
+                                         const T (&sg)[Q], Acc (&num)[Q], Acc (&den)[Q]) {
   constexpr int CH = 64;
   const int lim = TAIL ? cnt : kTile;
   if constexpr (KH) {
@@ -100,8 +107,8 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
         if constexpr (DIAG) {
           if (jt + jj == qi[k]) w = T(0);
         }
-        kahan_add(nh[k], nl[k], w * dv);
-        kahan_add(dh[k], dl[k], w);
+        num[k].add(w * dv);
+        den[k].add(w);
       }
     }
     return;
@@ -132,8 +139,8 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      two_sum_acc(nh[k], nl[k], an[k]);
-      two_sum_acc(dh[k], dl[k], ad[k]);
+      num[k].add(an[k]);
+      den[k].add(ad[k]);
     }
   };
   // Unrolled over the tile, the compiler keeps every 64-record block's partial sums live
@@ -211,9 +218,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 #pragma unroll
     for (int d = 0; d < 3; ++d) qc[k][d] = c[d] * s;
   }
-  T nh[Q], nl[Q], dh[Q], dl[Q];
+  using Acc = std::conditional_t<KH, KahanSum<T>, BlockSum<T>>;
+  Acc nacc[Q], dacc[Q];
 #pragma unroll
-  for (int k = 0; k < Q; ++k) nh[k] = nl[k] = dh[k] = dl[k] = T(0);
+  for (int k = 0; k < Q; ++k) {
+    nacc[k].zero();
+    dacc[k].zero();
+  }
 
   T rc[2][3], rv[2];
   auto fetch = [&](int t) {
@@ -246,13 +257,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
     const bool diag = excl && jt < q0 + kWG * Q && q0 < jt + kTile;
     if (cnt < kTile) {
       if (diag)
-        fwd_tile<T, DIM, PM, Q, true, 1, KH, REL, true>(tile[t & 1], jt, cnt, qc, qi, nhp, sg, nh, nl, dh, dl);
+        fwd_tile<T, DIM, PM, Q, true, 1, KH, REL, true>(tile[t & 1], jt, cnt, qc, qi, nhp, sg, nacc, dacc);
       else
-        fwd_tile<T, DIM, PM, Q, false, 1, KH, REL, true>(tile[t & 1], jt, cnt, qc, qi, nhp, sg, nh, nl, dh, dl);
+        fwd_tile<T, DIM, PM, Q, false, 1, KH, REL, true>(tile[t & 1], jt, cnt, qc, qi, nhp, sg, nacc, dacc);
     } else if (diag) {
-      fwd_tile<T, DIM, PM, Q, true, 1, KH, REL>(tile[t & 1], jt, kTile, qc, qi, nhp, sg, nh, nl, dh, dl);
+      fwd_tile<T, DIM, PM, Q, true, 1, KH, REL>(tile[t & 1], jt, kTile, qc, qi, nhp, sg, nacc, dacc);
     } else {
-      fwd_tile<T, DIM, PM, Q, false, UNR, KH, REL>(tile[t & 1], jt, kTile, qc, qi, nhp, sg, nh, nl, dh, dl);
+      fwd_tile<T, DIM, PM, Q, false, UNR, KH, REL>(tile[t & 1], jt, kTile, qc, qi, nhp, sg, nacc, dacc);
     }
     if (t + 1 < ntiles) put((t + 1) & 1);
     __syncthreads();
@@ -261,8 +272,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) v
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     if (qi[k] < m) {
-      double num = static_cast<double>(nh[k]) + static_cast<double>(nl[k]);
-      double den = static_cast<double>(dh[k]) + static_cast<double>(dl[k]);
+      double num = nacc[k].value();
+      double den = dacc[k].value();
       if constexpr (REL) {
         num *= fs[k];
         den *= fs[k];

@@ -78,14 +78,16 @@ enum {
 enum { IDW_SOA = 0, IDW_AOS = 1, IDW_AOAS = 2, IDW_HYBRID = 3, IDW_SOAOS = 4 };
 
 /* Precision of the sweep.
- *   IDW_FP32: float inputs/outputs.  The all-pairs sweep runs in FP32 with blocked
- *     compensated sums (plain FP32 inside 64-point blocks, TwoSum merge of each block into
- *     hi/lo pairs); the ratio is taken in FP64; queries closer than 1e-6 of the data
- *     extent to a data point (including exact hits) are recomputed entirely in FP64.
- *   IDW_FP64: double inputs/outputs, FP64 sweep with the same blocked compensation.
- *   IDW_FP32_KAHAN: as IDW_FP32, but the forward sweep updates its (hi, lo) sums with a
- *     Kahan step on every pair instead of per block (the accuracy variant; about 1.9x the
- *     forward's time).  idw_backward treats it as IDW_FP32; batched plans do not take it. */
+ *   IDW_FP32: float inputs/outputs.  The all-pairs sweep runs in FP32 with blocked sums
+ *     (plain FP32 inside 64-point blocks, each block sum added into an FP64 running sum);
+ *     the ratio is taken in FP64; queries closer than 1e-6 of the data extent to a data
+ *     point (including exact hits) are recomputed entirely in FP64.
+ *   IDW_FP64: double inputs/outputs, FP64 sweep with plain FP64 sums inside 64-point
+ *     blocks, each block sum merged into a (hi, lo) pair with TwoSum.
+ *   IDW_FP32_KAHAN: as IDW_FP32, but the forward sweep updates FP32 (sum, error) pairs with
+ *     a Kahan step on every pair instead of summing per block (the accuracy variant; about
+ *     1.6x the forward's time).  idw_backward treats it as IDW_FP32; batched plans do not
+ *     take it. */
 enum { IDW_FP32 = 0, IDW_FP64 = 1, IDW_FP32_KAHAN = 2 };
 
 /* Flags. */
@@ -181,13 +183,16 @@ int idw_forward(const idw_points* data, const idw_points* query, double p, int32
                 size_t workspace_bytes, void* stream, const idw_config* cfg);
 
 /* idw_forward for callers that cannot allocate device memory (code under HIP graph
- * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation and
- * results, bit for bit, with the workspace taken from a static device array of the library
- * (64 MiB per device, held from the first call on that device until the process ends)
- * instead of a caller buffer.  The caller still passes the point sets and out_z / out_den
- * as for idw_forward.  Sizes whose forward workspace (idw_workspace_size with no IDW_NEED_*
- * bit) exceeds 64 MiB are rejected with IDW_EWORKSPACE before anything is enqueued; the
- * benchmark size n = m = 2^20 fits in both precisions.  Allocates nothing and calls no
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation,
+ * with the workspace taken from a static device array of the library (64 MiB per device,
+ * held from the first call on that device until the process ends) instead of a caller
+ * buffer.  The caller still passes the point sets and out_z / out_den as for idw_forward.
+ * With cfg->split 0, where the default data split's partial sums do not fit the array, the
+ * largest split that fits is taken: the results are then bit for bit those of idw_forward
+ * given that split in cfg (otherwise those of idw_forward with the same cfg).  Sizes whose
+ * forward workspace (idw_workspace_size with no IDW_NEED_* bit) exceeds 64 MiB even
+ * unsplit are rejected with IDW_EWORKSPACE before anything is enqueued; the benchmark size
+ * n = m = 2^20 fits in both precisions.  Allocates nothing and calls no
  * allocating routine.  Every call on a device uses that device's one array, and leaves
  * its contents behind: calls that overlap on one device (other streams, other threads, or
  * a second call before the first has completed on a different stream) race and give

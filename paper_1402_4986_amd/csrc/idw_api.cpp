@@ -3,6 +3,7 @@
 // device memory or synchronises.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -171,15 +172,24 @@ int pmode_of(double p) {
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-// Splits `len` points into chunks (multiples of the tile) so that `blocks` x chunks fills
-// the chip (about 2 workgroups per compute unit), with at least 4 tiles per chunk.
-static void choose_split(int64_t len, int64_t blocks, int want_split, int& split, int64_t& chunk) {
-  int s = want_split;
+// Partial sums of the split sweeps are kept within this many bytes per array (the chunk
+// count is capped by it); the fused adjoint's two partial arrays likewise.
+constexpr int64_t kPartBudget = int64_t(1) << 31;
+
+// Splits `len` points into chunks (multiples of the tile) so that `blocks` x chunks is about
+// 16384 workgroups, at least 4 tiles per chunk and at most kPartBudget bytes of partials
+// (`unit` bytes per chunk and element of the other set, `other` elements).  Every workgroup
+// does the same work, and a grid of 1024 workgroups (one per 1024-query block at 1M
+// queries) on the 768 that are resident at once loses about 7% to the last, partly empty
+// round; with 16 times as many the loss is below 1% (1M x 1M forward: 204.1 -> 189.2 ms).
+static void choose_split(int64_t len, int64_t blocks, int want_split, int64_t unit, int64_t other, int& split,
+                         int64_t& chunk) {
+  int64_t s = want_split;
   if (s <= 0) {
-    const int64_t target = 512;
-    s = static_cast<int>(cdiv(target, blocks > 0 ? blocks : 1));
-    const int64_t maxs = cdiv(len, 4 * kTile);
-    if (s > maxs) s = static_cast<int>(maxs);
+    const int64_t target = 16384;
+    s = cdiv(target, blocks > 0 ? blocks : 1);
+    s = std::min<int64_t>(s, cdiv(len, 4 * kTile));
+    s = std::min<int64_t>(s, std::max<int64_t>(1, kPartBudget / (unit * std::max<int64_t>(other, 1))));
   }
   if (s < 1) s = 1;
   if (s > 1024) s = 1024;
@@ -194,23 +204,28 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
   const int64_t n = data->n, m = query->n;
   // forward
   w.qf = (cfg && cfg->queries_per_lane) ? cfg->queries_per_lane : 4;
-  choose_split(n, cdiv(m, kWG * w.qf), cfg ? cfg->split : 0, w.split_f, w.chunk_f);
+  choose_split(n, cdiv(m, kWG * w.qf), cfg ? cfg->split : 0, sizeof(double2), m, w.split_f, w.chunk_f);
   // backward: query sweep over data chunks, data sweep over query chunks
   w.qq = 2;
-  choose_split(n, cdiv(m, kWG * w.qq), 0, w.split_q, w.chunk_q);
+  choose_split(n, cdiv(m, kWG * w.qq), 0, sizeof(double4), m, w.split_q, w.chunk_q);
   w.qz = f64 ? 2 : 4;
-  choose_split(m > 0 ? m : 1, cdiv(n, kWG * w.qz), 0, w.split_z, w.chunk_z);
+  choose_split(m > 0 ? m : 1, cdiv(n, kWG * w.qz), 0, sizeof(double), n, w.split_z, w.chunk_z);
   // fused adjoint: workgroup (group, range) sweeps data range `range` for the query blocks
-  // group, group + G, ...; in FP32 about 1024 workgroups of 512 threads in all, in FP64
-  // about 2048 of 256.  Ranges of 64K points balance the dz rows (groups x n doubles)
-  // against the query partials (ranges x m double4): about 1 GB at n = m = 1M in FP32.
+  // group, group + G, ...: about 8192 workgroups in all (of 512 threads in FP32, 256 in
+  // FP64), for the reason given at choose_split (1M x 1M: 377.3 ms with 1024, 353.4 with
+  // 8192).  Ranges of at most 32K points (at least one tile) and as many groups as the
+  // query blocks allow, within kPartBudget for the dz rows (groups x n doubles) and for
+  // the query partials (ranges x m double4): 2 GB and 1 GB at n = m = 1M.
   if (m > 0) {
-    const int ranges = static_cast<int>(std::min<int64_t>(64, std::max<int64_t>(1, cdiv(n, 65536))));
-    w.fused_chunk = cdiv(cdiv(n, ranges), kTile) * kTile;
-    w.fused_ranges = static_cast<int>(cdiv(n, w.fused_chunk));
+    const int64_t target = 8192;
     const int64_t nqb = cdiv(m, f64 ? 256 * 2 : 512 * 2);
-    const int64_t target = f64 ? 2048 : 1024;
-    w.fused_groups = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(nqb, cdiv(target, w.fused_ranges))));
+    int64_t r = std::max<int64_t>(cdiv(n, 32768), cdiv(target, nqb));
+    r = std::min<int64_t>(r, std::min<int64_t>(cdiv(n, kTile), std::max<int64_t>(1, kPartBudget / (32 * m))));
+    r = std::max<int64_t>(r, 1);
+    w.fused_chunk = cdiv(cdiv(n, r), kTile) * kTile;
+    w.fused_ranges = static_cast<int>(cdiv(n, w.fused_chunk));
+    const int64_t gcap = std::min<int64_t>(nqb, std::max<int64_t>(1, kPartBudget / (8 * n)));
+    w.fused_groups = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(gcap, cdiv(target, w.fused_ranges))));
   }
   w.nbbox = static_cast<int>(std::min<int64_t>(1024, cdiv(n, kWG)));
   w.nwg_dp = static_cast<int>(cdiv(m, kWG));
@@ -551,8 +566,18 @@ static int forward_impl(const idw_points* data, const idw_points* query, double 
   const int64_t m = query->n;
   if (m == 0) return IDW_OK;
   if (!out_z) return fail(IDW_EINVAL, "out_z is null");
-  const WsPlan w = plan_workspace(data, query, precision, cfg);
+  WsPlan w = plan_workspace(data, query, precision, cfg);
   if (static_scratch) {
+    // Where the default data split's partial sums do not fit the scratch, take the largest
+    // split that does (the same result as idw_forward with that split in cfg).
+    if (w.fwd_total > kScratchBytes && !(cfg && cfg->split) && w.split_f > 1) {
+      idw_config c{};
+      if (cfg) c = *cfg;
+      for (c.split = w.split_f - 1; c.split >= 1; --c.split) {
+        w = plan_workspace(data, query, precision, &c);
+        if (w.fwd_total <= kScratchBytes) break;
+      }
+    }
     if (w.fwd_total > kScratchBytes)
       return fail(IDW_EWORKSPACE, "idw_forward_noalloc: these sizes need %zu bytes of scratch, above its %zu",
                   w.fwd_total, kScratchBytes);

@@ -142,10 +142,16 @@ def test_noalloc_forward_checks_its_scratch_limit_on_the_host(lib):
     assert call(d, q, prec=7) == _lib.IDW_EINVAL
     q0 = _pts(0, 2, _lib.AOAS)
     assert call(d, q0) == 0                          # no queries: a no-op, as idw_forward
-    # the benchmark size fits the scratch in both precisions
+    # the benchmark size fits the scratch in both precisions once the data split is small
+    # enough (the entry point takes the largest split that fits; the default one does not)
     for prec in (_lib.FP32, _lib.FP64):
         s = _pts(1 << 20, 2, _lib.AOAS)
         assert lib.idw_workspace_size(ctypes.byref(s), ctypes.byref(s), prec, 0, None, ctypes.byref(b)) == 0
+        assert b.value > 64 << 20
+        cfg = _lib.IdwConfig()
+        cfg.split = 1
+        assert lib.idw_workspace_size(ctypes.byref(s), ctypes.byref(s), prec, 0, ctypes.byref(cfg),
+                                      ctypes.byref(b)) == 0
         assert b.value <= 64 << 20
 
 

@@ -179,13 +179,13 @@ def test_fused_and_separate_adjoint_sweeps(separate, dim, p):
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_fused_adjoint_accumulates_over_query_blocks(prec):
-    # 1,000,000 data points in 16 ranges and 100,000 queries: in FP32, 98 blocks of 1,024
-    # queries on 64 workgroup groups; in FP64, 196 blocks of 512 on 128 groups.  Each group
-    # folds one or two query blocks into its dz row.  The upstream gradient is non-zero on
-    # 150 scattered queries only, so the oracle needs just those queries for the exact dz,
-    # dp and dq.
+    # 1,000,000 data points in 31 ranges and 600,000 queries: in FP32, 586 blocks of 1,024
+    # queries on 265 workgroup groups; in FP64, 1,172 blocks of 512 on the same 265 groups.
+    # Each group folds two or three (FP64: four or five) query blocks into its dz row.  The
+    # upstream gradient is non-zero on 150 scattered queries only, so the oracle needs just
+    # those queries for the exact dz, dp and dq.
     t = np.float32 if prec == "f32" else np.float64
-    x, z, q = rand_case(32, 1000000, 100000, 2, prec)
+    x, z, q = rand_case(32, 1000000, 600000, 2, prec)
     r = np.random.default_rng(33)
     sel = np.sort(r.choice(len(q), size=150, replace=False))
     g = np.zeros(len(q))

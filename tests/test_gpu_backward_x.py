@@ -112,15 +112,15 @@ def test_dx_and_dq_cancel_on_the_gpu():
 
 
 def test_fused_dx_accumulates_over_query_blocks():
-    # As for dz: 1,000,000 data points in 16 ranges, 100,000 queries in 98 blocks folded by
-    # 64 groups; the upstream gradient is non-zero on 150 queries only, so the oracle needs
+    # As for dz: 1,000,000 data points in 31 ranges, 600,000 queries in 586 blocks folded by
+    # 265 groups; the upstream gradient is non-zero on 150 queries only, so the oracle needs
     # just those queries.
-    x, z, q = rand_case(460, 1000000, 100000, 2)
+    x, z, q = rand_case(460, 1000000, 600000, 2)
     r = np.random.default_rng(461)
     sel = np.sort(r.choice(len(q), size=150, replace=False))
     g = np.zeros(len(q))
     g[sel] = r.normal(size=150).astype(np.float32)
-    print("fused dx, n=1e6 m=1e5", flush=True)
+    print("fused dx, n=1e6 m=6e5", flush=True)
     _, _, _, dx = _run(x, z, q, 2.0, "soa", "f32", g)
     _check_dx(dx, oracle.backward_x(x, z, q[sel], 2.0, g[sel]), "f32")
 

@@ -183,7 +183,7 @@ def test_full_size_plain2d_1m_adjoint_sparse_upstream(prec, plain2d_1m):
     # The full-size adjoint (dz, dp, dq) in the benchmark's launch configuration, with the
     # upstream gradient non-zero on the 4,096 sampled queries only: dz and dp are then sums
     # over those queries alone, which the oracle evaluates exactly.  Every workgroup group of
-    # the fused sweep folds 16 query blocks into its dz row at this size.
+    # the fused sweep folds 4 query blocks (FP64: 8) into its dz row at this size.
     x, z, q, idx, _ = plain2d_1m
     t = np.float32 if prec == "f32" else np.float64
     g = np.zeros(len(q))

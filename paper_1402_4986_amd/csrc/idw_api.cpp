@@ -559,8 +559,11 @@ static int forward_impl(const idw_points* data, const idw_points* query, double 
   if (flags & ~IDW_EXCLUDE_SELF) return fail(IDW_EINVAL, "idw_forward accepts only IDW_EXCLUDE_SELF");
   if (cfg && cfg->queries_per_lane) {
     const int q = cfg->queries_per_lane;
-    const bool ok = precision == IDW_FP64 ? (q == 2 || q == 4) : precision == IDW_FP32_KAHAN ? q == 4 : (q == 4 || q == 8);
-    if (!ok) return fail(IDW_EUNSUPPORTED, "queries_per_lane %d not built for this precision", q);
+    const bool ok = precision == IDW_FP64         ? (q == 2 || q == 4)
+                    : precision == IDW_FP32_KAHAN ? q == 4
+                    : p >= kRelP                  ? (q == 4 || q == 8)
+                                                  : (q == 2 || q == 4 || q == 8);
+    if (!ok) return fail(IDW_EUNSUPPORTED, "queries_per_lane %d not built for this precision and p", q);
   }
   if (cfg && (cfg->split < 0 || cfg->split > 1024)) return fail(IDW_EINVAL, "split must be in 0..1024");
   const int64_t m = query->n;
@@ -603,8 +606,13 @@ static int forward_impl(const idw_points* data, const idw_points* query, double 
   a.pmode = pmode_of(p);
   a.p = p;
   a.flags = flags;
-  a.q_per_lane = w.qf;
   a.kahan = precision == IDW_FP32_KAHAN;
+  // Queries per lane: 2 for the FP32 sweeps whose weight takes at most one transcendental
+  // (p = 1, 2, 3, 4), 4 otherwise (the plan's default, which also sets the data split).
+  a.q_per_lane = w.qf;
+  if (!(cfg && cfg->queries_per_lane) && precision == IDW_FP32 && p < kRelP &&
+      (a.pmode == PM_1 || a.pmode == PM_2 || a.pmode == PM_3 || a.pmode == PM_4))
+    a.q_per_lane = 2;
   // Large p in FP32: relative weights, sigma from each query's nearest distance.
   a.rel = !f64 && p >= kRelP;
   a.rmin = reinterpret_cast<const unsigned long long*>(ws + w.near_min);

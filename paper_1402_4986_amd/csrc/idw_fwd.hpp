@@ -136,6 +136,17 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
         an[k] = fmaT(w, dv, an[k]);
         ad[k] += w;
       }
+      // 2-D, one reciprocal per pair, 2 queries per lane: ask the scheduler to interleave
+      // each transcendental with six other VALU instructions rather than issue them in
+      // runs (1M x 1M p = 2 forward: 179.0 -> 175.6 ms; in 3-D and with 4 queries per lane
+      // it measured slower, so those keep the default order).
+      if constexpr (sizeof(T) == 4 && DIM == 2 && Q == 2 && (PM == PM_1 || PM == PM_2)) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // 6 VALU
+          __builtin_amdgcn_sched_group_barrier(0x400, 1, 0);  // 1 transcendental
+        }
+      }
     }
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -145,10 +156,13 @@ __device__ __forceinline__ void fwd_tile(const P4<T>* __restrict__ tl, int64_t j
   };
   // Unrolled over the tile, the compiler keeps every 64-record block's partial sums live
   // until the tile's end and merges them there (159 VGPRs for the FP32 p = 2 sweep against
-  // 95 block by block).  Measured at 1M x 1M: that is 3% faster at p = 2 (206.8 against
-  // 213.1 ms) but 5% slower for the general-p weight (299.8 against 285.9 ms at p = 1.7),
-  // whose exp2 / log2 need the registers; so general p goes block by block.
-  if constexpr (PM == PM_GEN) {
+  // 95 block by block).  Measured at 1M x 1M (16 data chunks): that is 3% faster for the
+  // one-transcendental FP32 weights (2-D p = 2: 188.4 against 193.7 ms; p = 1 and 3, and
+  // in 3-D, 4-6%) but slower where the weight needs two transcendentals or more registers:
+  // FP32 p = 4 (216.6 against 197.8 ms), p = 2.5 (302.0 against 279.2 ms; the 3-D
+  // mixture 87.5 against 81.2 ms) and the general-p exp2 / log2 (299.8 against 285.9 ms at
+  // p = 1.7), which go block by block.  FP64 differs by at most 2% either way.
+  if constexpr (PM == PM_GEN || (sizeof(T) == 4 && (PM == PM_4 || PM == PM_25))) {
 #pragma unroll 1
     for (int c0 = 0; c0 < lim; c0 += CH) block(c0);
   } else {
@@ -169,7 +183,10 @@ __device__ __forceinline__ void fwd_finish(int64_t i, double num, double den, co
 // Register-blocking and occupancy knobs of a sweep kernel: UNR = unroll of the per-record
 // loop, WPE = minimum waves per SIMD the register allocation must allow.
 // Values measured on MI355X (1M queries x 128K data, 2-D, p = 2): FP32 Q = 4 with a 4-deep
-// unroll issues 7.4 VALU lane-slots per pair against 8.3 for Q = 8.
+// unroll issues 7.4 VALU lane-slots per pair against 8.3 for Q = 8.  With the 16-chunk
+// launch at 1M x 1M, Q = 2 (unroll 4) is faster still for the weights with at most one
+// transcendental (p = 2: 189.1 -> 179.0 ms; p = 3: 231.4 -> 223.2 ms; 3-D p = 2: 57.8 ->
+// 55.0 ms) and within 1% for p = 2.5 and general p, which keep Q = 4.
 template <typename T, int Q>
 struct SweepTune {
   static constexpr int UNR = (Q >= 8) ? 2 : 4;
@@ -615,6 +632,7 @@ hipError_t launch_fwd_sweep_q(const FwdArgs& a, hipStream_t st) {
       return hipGetLastError();
     }
     switch (Q) {
+      IDW_FWD_Q(2)
       IDW_FWD_Q(4)
       IDW_FWD_Q(8)
       default:

@@ -253,6 +253,21 @@ def test_kahan_precision_is_fp32_storage_with_its_own_limits(lib):
     assert lib.idw_batched_plan_create(arr, 1, _lib.FP32_KAHAN, None, ctypes.byref(plan)) == _lib.IDW_EUNSUPPORTED
 
 
+def test_queries_per_lane_builds(lib):
+    # FP32 builds 2, 4 and 8 queries per lane, but the relative-weight sweep (p >= 6) only 4
+    # and 8; FP64 builds 2 and 4.  Refused combinations fail on the host with
+    # IDW_EUNSUPPORTED before anything is enqueued (null stream, fake device pointers).
+    d = _pts(1000, 2, _lib.AOAS)
+    q = _pts(500, 2, _lib.AOAS, base=0x20000000)
+    cfg = _lib.IdwConfig()
+    for prec, qpl, p in ((_lib.FP32, 2, 8.0), (_lib.FP32, 16, 2.0), (_lib.FP64, 8, 2.0), (_lib.FP32_KAHAN, 2, 2.0)):
+        cfg.queries_per_lane = qpl
+        rc = lib.idw_forward(ctypes.byref(d), ctypes.byref(q), p, prec, 0, 0x8000000, None, 0x4000000, 1 << 30,
+                             None, ctypes.byref(cfg))
+        assert rc == _lib.IDW_EUNSUPPORTED, (prec, qpl, p)
+        assert "queries_per_lane" in lib.idw_last_error().decode()
+
+
 @pytest.mark.parametrize("field,value", [("reserved", 1), ("split", -1), ("queries_per_lane", -4),
                                          ("batch_chunk", -1), ("separate_adjoint", 2), ("near_search", 2),
                                          ("near_search", -1)])

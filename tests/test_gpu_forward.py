@@ -76,7 +76,7 @@ def test_data_split_merges_to_the_same_result(split):
     assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
 
 
-@pytest.mark.parametrize("qpl", [4, 8])
+@pytest.mark.parametrize("qpl", [2, 4, 8])
 def test_queries_per_lane_variants(qpl):
     x, z, q = rand_case(10, 5000, 3000, 3)
     Z, _ = gpu_forward(x, z, q, 3.0, "soa", "f32", queries_per_lane=qpl)

@@ -221,6 +221,7 @@ WsPlan plan_workspace(const idw_points* data, const idw_points* query, int preci
     const int64_t nqb = cdiv(m, f64 ? 256 * 2 : 512 * 2);
     int64_t r = std::max<int64_t>(cdiv(n, 32768), cdiv(target, nqb));
     r = std::min<int64_t>(r, std::min<int64_t>(cdiv(n, kTile), std::max<int64_t>(1, kPartBudget / (32 * m))));
+    r = std::min<int64_t>(r, 32768);  // grid y dimension
     r = std::max<int64_t>(r, 1);
     w.fused_chunk = cdiv(cdiv(n, r), kTile) * kTile;
     w.fused_ranges = static_cast<int>(cdiv(n, w.fused_chunk));
@@ -608,10 +609,12 @@ static int forward_impl(const idw_points* data, const idw_points* query, double 
   a.flags = flags;
   a.kahan = precision == IDW_FP32_KAHAN;
   // Queries per lane: 2 for the FP32 sweeps whose weight takes at most one transcendental
-  // (p = 1, 2, 3, 4), 4 otherwise (the plan's default, which also sets the data split).
+  // (p = 1, 2, 3, 4) and for every FP64 sweep (general p 1036 -> 957 ms at 1M x 1M; the
+  // others within 1.2%), 4 otherwise (the plan's default, which also sets the data split).
   a.q_per_lane = w.qf;
-  if (!(cfg && cfg->queries_per_lane) && precision == IDW_FP32 && p < kRelP &&
-      (a.pmode == PM_1 || a.pmode == PM_2 || a.pmode == PM_3 || a.pmode == PM_4))
+  if (!(cfg && cfg->queries_per_lane) &&
+      (f64 || (precision == IDW_FP32 && p < kRelP &&
+               (a.pmode == PM_1 || a.pmode == PM_2 || a.pmode == PM_3 || a.pmode == PM_4))))
     a.q_per_lane = 2;
   // Large p in FP32: relative weights, sigma from each query's nearest distance.
   a.rel = !f64 && p >= kRelP;

@@ -186,7 +186,8 @@ __device__ __forceinline__ void fwd_finish(int64_t i, double num, double den, co
 // unroll issues 7.4 VALU lane-slots per pair against 8.3 for Q = 8.  With the 16-chunk
 // launch at 1M x 1M, Q = 2 (unroll 4) is faster still for the weights with at most one
 // transcendental (p = 2: 189.1 -> 179.0 ms; p = 3: 231.4 -> 223.2 ms; 3-D p = 2: 57.8 ->
-// 55.0 ms) and within 1% for p = 2.5 and general p, which keep Q = 4.
+// 55.0 ms) and within 1% for p = 2.5 and general p, which keep Q = 4.  In FP64, Q = 2 is
+// faster for general p (1036 -> 957 ms) and within 1.2% elsewhere; the FP64 sweeps take it.
 template <typename T, int Q>
 struct SweepTune {
   static constexpr int UNR = (Q >= 8) ? 2 : 4;

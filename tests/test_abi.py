@@ -161,6 +161,19 @@ def test_zero_queries_is_a_no_op(lib):
     assert _fwd(lib, d, q, out=0) == 0
 
 
+@pytest.mark.parametrize("n", [1, 1000, 1 << 16, 1 << 20, 1 << 24, 2 ** 31 - 1])
+@pytest.mark.parametrize("m", [1, 1000, 1 << 16, 1 << 20, 1 << 24, 2 ** 31 - 1])
+def test_adjoint_workspace_stays_bounded(lib, n, m):
+    # The launch shapes grow the partial-sum arrays with the grid, each kept within 2 GiB
+    # (or one row of the point set): the forward + adjoint workspace stays below
+    # 4.5 GiB + 16 B per data point + 128 B per query at every size the boundary accepts.
+    d, q = _pts(n, 2, _lib.AOAS), _pts(m, 2, _lib.AOAS, base=0x20000000)
+    b = ctypes.c_size_t()
+    flags = _lib.NEED_DZ | _lib.NEED_DP | _lib.NEED_DQ
+    assert lib.idw_workspace_size(ctypes.byref(d), ctypes.byref(q), _lib.FP32, flags, None, ctypes.byref(b)) == 0
+    assert b.value <= 4.5 * (1 << 30) + 16 * n + 128 * m
+
+
 def test_workspace_size_grows_with_queries(lib):
     d = _pts(4096, 2, _lib.SOA)
     sizes = []

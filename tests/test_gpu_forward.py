@@ -76,12 +76,15 @@ def test_data_split_merges_to_the_same_result(split):
     assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
 
 
-@pytest.mark.parametrize("qpl", [2, 4, 8])
-def test_queries_per_lane_variants(qpl):
-    x, z, q = rand_case(10, 5000, 3000, 3)
-    Z, _ = gpu_forward(x, z, q, 3.0, "soa", "f32", queries_per_lane=qpl)
-    ref = oracle.forward(x, z, q, 3.0)
-    assert np.max(scaled_err(Z, ref)) <= TOL["f32"]
+@pytest.mark.parametrize("prec,qpl", [("f32", 2), ("f32", 4), ("f32", 8), ("f64", 2), ("f64", 4)])
+@pytest.mark.parametrize("dim,p", [(2, 2.0), (3, 3.0), (2, 1.7)])
+def test_queries_per_lane_variants(prec, qpl, dim, p):
+    # Every queries-per-lane build against the oracle (the defaults are 2 for FP64 and for
+    # the FP32 weights with one transcendental, 4 otherwise), with a ragged last block.
+    x, z, q = rand_case(10, 5000, 3001, dim, prec)
+    Z, _ = gpu_forward(x, z, q, p, "soa", prec, queries_per_lane=qpl)
+    ref = oracle.forward(x, z, q, p)
+    assert np.max(scaled_err(Z, ref)) <= TOL[prec]
 
 
 def test_tiny_and_degenerate_sizes():

@@ -108,10 +108,14 @@ typedef struct idw_points {
 } idw_points;
 
 /* Optional launch configuration; zero fields select the library default.
- *   queries_per_lane  queries held in registers per lane of the forward sweep (FP32: 4 or
- *                     8; FP32_KAHAN: 4; FP64: 2 or 4; default 4)
+ *   queries_per_lane  queries held in registers per lane of the forward sweep (FP32: 2, 4
+ *                     or 8, and 4 or 8 for p >= 6; FP32_KAHAN: 4; FP64: 2 or 4; others
+ *                     are refused with IDW_EUNSUPPORTED); 0 = FP64: 2; FP32: 2 for p = 1,
+ *                     2, 3, 4, else 4 (the default split is computed for 4 then).
  *   split             number of data chunks swept by separate workgroups and merged in a
- *                     fixed order (1..1024); 0 = chosen from m so the chip is filled
+ *                     fixed order (1..1024); 0 = chosen from n and m so the grid has about
+ *                     16384 workgroups, each chunk at least 2048 points, and the partial
+ *                     sums take at most 2 GiB
  *   batch_chunk       batched plans: data points per work item (rounded up to 512;
  *                     default: the autotuned value compiled into the library, see
  *                     idw_batched_defaults)

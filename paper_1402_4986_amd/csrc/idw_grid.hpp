@@ -33,9 +33,14 @@
 namespace idw {
 
 // Dense cells: the per-query budget of the fixed-radius check and the ring search before
-// a query is handed to the brute-force kernels.
+// a query is handed to the brute-force kernels.  The ring search's cell budget is per
+// dimension: in 3-D a query in empty space between clusters visits (2r + 1)^3 cells by
+// ring r, and past two rings a failing search costs more than it saves (262,144 points in
+// 16 clusters, 1M uniform queries, p = 8: 147 ms forward with 512 cells, 134 ms with 125;
+// uniform 3-D points need at most 2 rings and are unchanged at 80 ms).
 constexpr int kGridCapPoints = 4096;
-constexpr int kGridCapCells = 512;
+constexpr int kGridCapCells2 = 512;  // 2-D
+constexpr int kGridCapCells3 = 125;  // 3-D: rings 0..2
 constexpr int kGridMaxRing = 8;
 
 struct GridGeom {
@@ -246,7 +251,7 @@ __global__ __launch_bounds__(kWG) void k_grid_nearest(DevPts query, const double
             const int id = (z * G.g[1] + y) * G.g[0] + x;
             const int b = start[id], e = start[id + 1];
             points += e - b;
-            if (++cells > kGridCapCells || points > kGridCapPoints) {
+            if (++cells > (DIM == 3 ? kGridCapCells3 : kGridCapCells2) || points > kGridCapPoints) {
               over = true;
               break;
             }

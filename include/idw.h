@@ -167,9 +167,8 @@ int idw_record_bytes(int32_t layout, int32_t dim, int32_t precision, int32_t is_
  * adjoint per-range query partials and per-group data partials (3.2 GB there, plus
  * dim x 2.1 GB for IDW_NEED_DX); each such array stays within 2 GiB (dim times that for
  * the dx partials) or one row of the point set, whatever the sizes.  For 65,536 <= n <=
- * 2^26 (and
- * near_search = 0) the forward part holds the grid of the nearest-distance searches:
- * about 18 B per data point (34 B in FP64) and 4 B per query.  Host only. */
+ * 2^26 (and near_search = 0) the forward part holds the grid of the nearest-distance
+ * searches: about 18 B per data point (34 B in FP64) and 4 B per query.  Host only. */
 int idw_workspace_size(const idw_points* data, const idw_points* query, int32_t precision,
                        uint32_t flags, const idw_config* cfg, size_t* bytes);
 

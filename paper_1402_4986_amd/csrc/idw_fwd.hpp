@@ -188,16 +188,20 @@ __device__ __forceinline__ void fwd_finish(int64_t i, double num, double den, co
 // transcendental (p = 2: 189.1 -> 179.0 ms; p = 3: 231.4 -> 223.2 ms; 3-D p = 2: 57.8 ->
 // 55.0 ms) and within 1% for p = 2.5 and general p, which keep Q = 4.  In FP64, Q = 2 is
 // faster for general p (1036 -> 957 ms) and within 1.2% elsewhere; the FP64 sweeps take it.
-template <typename T, int Q>
+// At Q = 2 a deeper unroll pays for p = 3 in 2-D (16-deep: 224.5 -> 214.4 ms; 3-D mixture
+// 66.5 -> 68.5 ms, so 3-D keeps 4) and for p = 4 (8-deep: 190.8 -> 188.3 ms, 3-D mixture
+// 60.6 -> 59.0 ms); for p = 1 and 2 and in FP64 it is 1-3% slower.
+template <typename T, int Q, int PM = PM_GEN, int DIM = 2>
 struct SweepTune {
-  static constexpr int UNR = (Q >= 8) ? 2 : 4;
+  static constexpr bool kQ2 = sizeof(T) == 4 && Q == 2;
+  static constexpr int UNR = Q >= 8 ? 2 : !kQ2 ? 4 : (PM == PM_3 && DIM == 2) ? 16 : PM == PM_4 ? 8 : 4;
   static constexpr int WPE = 1;
 };
 
 // REL: relative weights; rmin holds each query's nearest squared distance (FP32 bits,
 // scaled units, from k_near_check over all queries) and the sums leave the kernel
 // multiplied by sigma^(p/2), i.e. in scaled units like those of the direct form.
-template <typename T, int DIM, int L, int PM, int Q, int UNR = SweepTune<T, Q>::UNR,
+template <typename T, int DIM, int L, int PM, int Q, int UNR = SweepTune<T, Q, PM, DIM>::UNR,
           int WPE = SweepTune<T, Q>::WPE, bool KH = false, bool REL = false>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_fwd_sweep(DevPts data, int64_t n, DevPts query, int64_t m,
                                                    int64_t chunk, int split, T nhp, unsigned flags,

@@ -190,11 +190,21 @@ __device__ __forceinline__ void fwd_finish(int64_t i, double num, double den, co
 // faster for general p (1036 -> 957 ms) and within 1.2% elsewhere; the FP64 sweeps take it.
 // At Q = 2 a deeper unroll pays for p = 3 in 2-D (16-deep: 224.5 -> 214.4 ms; 3-D mixture
 // 66.5 -> 68.5 ms, so 3-D keeps 4) and for p = 4 (8-deep: 190.8 -> 188.3 ms, 3-D mixture
-// 60.6 -> 59.0 ms); for p = 1 and 2 and in FP64 it is 1-3% slower.
-template <typename T, int Q, int PM = PM_GEN, int DIM = 2>
+// 60.6 -> 59.0 ms); for p = 1 and 2 and in FP64 it is 1-3% slower.  At Q = 4 an 8-deep
+// unroll pays for the per-pair Kahan sums (3-D mixture, p = 2.5: 130.5 -> 122.9 ms) and the
+// relative weights (2-D p = 8: 301.9 -> 285.2 ms) but not for the plain weights (2-D p = 1.5
+// 258.9 -> 263.2 ms, p = 2.5 279.1 -> 285.0 ms); the FP64 general-p sweep is faster 2-deep
+// (p = 1.7: 931 -> 894 ms, p = 2: 359 -> 364 ms, so only general p takes it).
+template <typename T, int Q, int PM = PM_GEN, int DIM = 2, bool KH = false, bool REL = false>
 struct SweepTune {
-  static constexpr bool kQ2 = sizeof(T) == 4 && Q == 2;
-  static constexpr int UNR = Q >= 8 ? 2 : !kQ2 ? 4 : (PM == PM_3 && DIM == 2) ? 16 : PM == PM_4 ? 8 : 4;
+  static constexpr bool kF32 = sizeof(T) == 4;
+  static constexpr int UNR = Q >= 8                            ? 2
+                             : (kF32 && Q == 4 && (KH || REL)) ? 8
+                             : (!kF32 && Q == 2 && PM == PM_GEN) ? 2
+                             : (!kF32 || Q != 2)               ? 4
+                             : (PM == PM_3 && DIM == 2)        ? 16
+                             : PM == PM_4                      ? 8
+                                                               : 4;
   static constexpr int WPE = 1;
 };
 
@@ -607,17 +617,19 @@ hipError_t launch_fwd_sweep_q(const FwdArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, QQ>), grid, dim3(kWG), 0, st, IDW_FWD_ARGS); \
     break;
   if constexpr (sizeof(T) == 4) {
-    using K4 = SweepTune<T, 4>;
+    using KK = SweepTune<T, 4, PM, DIM, true>;         // per-pair Kahan
+    using KR = SweepTune<T, 4, PM, DIM, false, true>;  // relative weights
+    using KKR = SweepTune<T, 4, PM, DIM, true, true>;
     using K8 = SweepTune<T, 8>;
     if (a.rel) {  // relative weights: general-p form only
       if constexpr (PM == PM_GEN) {
         if (!a.rmin) return hipErrorInvalidValue;
         if (a.kahan) {
           if (Q != 4) return hipErrorInvalidValue;
-          hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, K4::UNR, K4::WPE, true, true>), grid, dim3(kWG), 0, st,
-                             IDW_FWD_ARGS);
+          hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, KKR::UNR, KKR::WPE, true, true>), grid, dim3(kWG), 0,
+                             st, IDW_FWD_ARGS);
         } else if (Q == 4) {
-          hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, K4::UNR, K4::WPE, false, true>), grid, dim3(kWG), 0,
+          hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, KR::UNR, KR::WPE, false, true>), grid, dim3(kWG), 0,
                              st, IDW_FWD_ARGS);
         } else if (Q == 8) {
           hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 8, K8::UNR, K8::WPE, false, true>), grid, dim3(kWG), 0,
@@ -632,7 +644,7 @@ hipError_t launch_fwd_sweep_q(const FwdArgs& a, hipStream_t st) {
     }
     if (a.kahan) {  // per-pair Kahan variant, 4 queries per lane
       if (Q != 4) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, K4::UNR, K4::WPE, true>), grid, dim3(kWG), 0, st,
+      hipLaunchKernelGGL((k_fwd_sweep<T, DIM, L, PM, 4, KK::UNR, KK::WPE, true>), grid, dim3(kWG), 0, st,
                          IDW_FWD_ARGS);
       return hipGetLastError();
     }

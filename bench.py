@@ -41,10 +41,10 @@ FLOP_PER_PAIR_DX = {"bwd_data": 15, "bwd_fused": 23}
 def fwd_flop_per_pair(dim: int, p: float) -> int:
     """Algorithmic FLOP per pair of the forward sweep by weight class (same convention):
     r^2 is dim sub, mul and dim - 1 fma; the weight is rcp (p = 2), rsq (p = 1), rsq and two
-    mul (p = 3), rsq, mul, sqrt and mul (p = 2.5), or log2, mul and exp2 (general p); the
-    accumulation is fma (num) and add (den)."""
+    mul (p = 3), rcp and mul (p = 4), rsq, mul, sqrt and mul (p = 2.5), or log2, mul and exp2
+    (general p); the accumulation is fma (num) and add (den)."""
     r2 = dim + 1 + 2 * (dim - 1)
-    w = {1.0: 1, 2.0: 1, 3.0: 3, 2.5: 4}.get(float(p), 3)
+    w = {1.0: 1, 2.0: 1, 3.0: 3, 4.0: 2, 2.5: 4}.get(float(p), 3)
     return r2 + w + 3
 
 

@@ -177,18 +177,25 @@ static size_t al256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 constexpr int64_t kPartBudget = int64_t(1) << 31;
 
 // Splits `len` points into chunks (multiples of the tile) so that `blocks` x chunks is about
-// 16384 workgroups, at least 4 tiles per chunk and at most kPartBudget bytes of partials
-// (`unit` bytes per chunk and element of the other set, `other` elements).  Every workgroup
-// does the same work, and a grid of 1024 workgroups (one per 1024-query block at 1M
-// queries) on the 768 that are resident at once loses about 7% to the last, partly empty
-// round; with 16 times as many the loss is below 1% (1M x 1M forward: 204.1 -> 189.2 ms).
+// 16384 workgroups, at least 4 tiles per chunk (1 where 4 would leave fewer than 2048
+// workgroups) and at most kPartBudget bytes of partials (`unit` bytes per chunk and element
+// of the other set, `other` elements).  Every workgroup does the same work, and a grid of
+// 1024 workgroups (one per 1024-query block at 1M queries) on the 768 that are resident at
+// once loses about 7% to the last, partly empty round; with 16 times as many the loss is
+// below 1% (1M x 1M forward: 204.1 -> 189.2 ms).  Below a few tens of thousands of queries
+// even 4-tile chunks leave most of the chip idle (10,240^2 forward call, FP64: 166 us with 5
+// chunks, 102 us with 20; 32,768^2 FP32: 268 -> 250 us), while from 65,536^2 on the longer
+// merge of finer splits outweighs the fuller grid (65,536^2: 789 us with 32 chunks, 803
+// with 128), so the smaller minimum applies only to the small grids.
 static void choose_split(int64_t len, int64_t blocks, int want_split, int64_t unit, int64_t other, int& split,
                          int64_t& chunk) {
   int64_t s = want_split;
   if (s <= 0) {
     const int64_t target = 16384;
-    s = cdiv(target, blocks > 0 ? blocks : 1);
-    s = std::min<int64_t>(s, cdiv(len, 4 * kTile));
+    const int64_t b = blocks > 0 ? blocks : 1;
+    s = cdiv(target, b);
+    const int64_t s4 = cdiv(len, 4 * kTile);
+    s = std::min<int64_t>(s, b * s4 < 2048 ? cdiv(len, kTile) : s4);
     s = std::min<int64_t>(s, std::max<int64_t>(1, kPartBudget / (unit * std::max<int64_t>(other, 1))));
   }
   if (s < 1) s = 1;

@@ -1,9 +1,10 @@
 """Launch shapes against the oracle: sizes chosen around the decompositions the library picks.
 
-The forward cuts the data into chunks (at least 4 tiles of 512 points) for about 16384
-workgroups; the fused adjoint cuts it into ranges of at most 32K points (at least one tile)
-for about 8192 workgroups over 1,024-query blocks (512 in FP64).  These cases put the last
-chunk or range down to a few points, give many ranges to a single query block, sit just
+The forward cuts the data into chunks (at least 4 tiles of 512 points, or 1 tile where 4
+would leave fewer than 2048 workgroups) for about 16384 workgroups; the fused adjoint cuts it
+into ranges of at most 32K points (at least one tile) for about 8192 workgroups over
+1,024-query blocks (512 in FP64).  These cases put the last chunk or range down to a few
+points, give many ranges to a single query block, sit just
 above and below the 32K range size and the 65,536-point grid threshold, and hand the fused
 adjoint one-point and one-tile data sets.  Forward, and adjoint (dz, dp, dq, and dx for the
 fused FP32 sweep), against the FP64 oracle at the usual tolerances.

@@ -114,8 +114,9 @@ typedef struct idw_points {
  *                     2, 3, 4, else 4 (the default split is computed for 4 then).
  *   split             number of data chunks swept by separate workgroups and merged in a
  *                     fixed order (1..1024); 0 = chosen from n and m so the grid has about
- *                     16384 workgroups, each chunk at least 2048 points, and the partial
- *                     sums take at most 2 GiB
+ *                     16384 workgroups, each chunk at least 2048 points (512 where 2048
+ *                     would leave fewer than 2048 workgroups), and the partial sums take
+ *                     at most 2 GiB
  *   batch_chunk       batched plans: data points per work item (rounded up to 512;
  *                     default: the autotuned value compiled into the library, see
  *                     idw_batched_defaults)

@@ -385,9 +385,8 @@ def main():
     achieved = FLOP_PER_PAIR[dom] * pairs / (kt[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                # the counters cover the kernels of the default step; with dx the fused sweep
-                # is another kernel, whose traffic was not measured
-                "traffic": None if args.need_dx and dom in FLOP_PER_PAIR_DX else load_traffic(dom)}
+                # with dx the fused sweep is another kernel, with a record of its own
+                "traffic": load_traffic(dom + "_dx" if args.need_dx and dom in FLOP_PER_PAIR_DX else dom)}
     total_flop = sum(FLOP_PER_PAIR[k] for k in kt) * pairs
     out = {"metric": METRIC, "value": pairs / (ms_step * 1e-3), "unit": "pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),

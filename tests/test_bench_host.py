@@ -52,6 +52,10 @@ def test_traffic_record_needs_matching_sources(monkeypatch):
     assert k["bytes_per_launch"] == pytest.approx(k["fetch_bytes"] + k["write_bytes"])
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: rec["source_hash"])
     assert bench.load_traffic("bwd_fused") == k["bytes_per_launch"]
+    # the sweep with the data-coordinate gradient is another kernel, with a record of its own
+    kx = rec["kernels"]["bwd_fused_dx"]
+    assert ", true, true, true, false," in kx["kernel"] and ", true, true, false, false," in k["kernel"]
+    assert bench.load_traffic("bwd_fused_dx") == kx["bytes_per_launch"]
     assert bench.load_traffic("no_such_kernel") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.load_traffic("bwd_fused") is None
